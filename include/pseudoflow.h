@@ -1,0 +1,173 @@
+/*
+ * pseudoflow.h -- C ABI of the MI355X (gfx950) pseudo-flow continuous max-flow
+ * solvers: entropic Bregman proximal label steps and Chambolle flow steps for
+ * the Potts, hierarchical (HMF) and DAG (DAGMF) models, and the Ishikawa chain
+ * (Baxter, Rajchl, Yuan, Peters, "A Proximal Bregman Projection Approach to
+ * Continuous Max-Flow Problems Using Entropic Distances").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid.     A batch of B independent problems on a Z x Y x X grid (2-D problems
+ *           have ndim == 2 and nz == 1).  Unit spacing; forward differences
+ *           with a zero gradient on the last index of each axis; the
+ *           divergence is the negative adjoint of that gradient.
+ * Layout.   Every field is a dense float array [B][F][Z][Y][X], x fastest.
+ *           Flows are [B][n_node][ndim][Z][Y][X], component k = axis x, y, z
+ *           for k = 0, 1, 2.
+ * Labels.   D holds one data term per end-label (leaf), leaves numbered in
+ *           ascending node id.  Internal labels carry no data term.
+ * Graphs.   Node 0 is the source.  Edge weights default to 1/|parents(child)|
+ *           and the weighted path sums from the source to every leaf must be 1.
+ * Memory.   Every device pointer is allocated and freed by the caller.  The
+ *           library never allocates device memory: the solver state lives in
+ *           the caller's workspace (pf_workspace_bytes), which also carries it
+ *           from one call to the next (warm_start).  Host arrays are read
+ *           during the call only.
+ * Streams.  Work is enqueued on `stream` (a hipStream_t; NULL is the default
+ *           stream).  The call returns without synchronising unless it must
+ *           read results back: gap_every > 0, final_energy, check_inputs or
+ *           timing_stride > 0.  Then it synchronises `stream` before returning.
+ * Errors.   The return value is a pf_status; pf_last_error() gives a message
+ *           (thread-local, valid until the next call on the thread).  Every
+ *           argument and graph check happens before the first launch and an
+ *           invalid call leaves all outputs untouched.  PF_EHIP reports a HIP
+ *           runtime failure and PF_ENONFINITE a NaN/Inf found by check_inputs
+ *           or by a gap evaluation; after those two, outputs are undefined.
+ */
+#ifndef PSEUDOFLOW_H
+#define PSEUDOFLOW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PF_ABI_VERSION 1
+#define PF_MAX_LEAVES 16     /* end-labels per problem */
+#define PF_MAX_NODES 32      /* non-source nodes per problem */
+
+typedef enum {
+    PF_OK = 0,
+    PF_EINVAL = -1,          /* bad argument (null/misaligned pointer, size, c, tau, ...) */
+    PF_EGRAPH = -2,          /* label graph rejected (cycle, orphan, weights, not a tree) */
+    PF_ENOMEM = -3,          /* workspace smaller than pf_workspace_bytes() */
+    PF_EHIP = -4,            /* HIP runtime error */
+    PF_ENONFINITE = -5,      /* NaN/Inf in the inputs or in a gap evaluation */
+    PF_EUNSUPPORTED = -6     /* valid but outside this build (too many labels, ...) */
+} pf_status;
+
+typedef enum { PF_FP32 = 0, PF_BF16 = 1, PF_FP16 = 2 } pf_storage;
+
+typedef enum {
+    PF_S_NODE_SCALAR = 0,    /* S: HOST float[n_node], one constant per flow */
+    PF_S_SHARED_FIELD = 1,   /* S: device float[B][Z][Y][X], shared by every flow */
+    PF_S_NODE_FIELD = 2      /* S: device float[B][n_node][Z][Y][X] */
+} pf_s_mode;
+
+typedef enum {
+    PF_KERNEL_AUTO = 0,      /* fused single pass where available */
+    PF_KERNEL_TWO_PASS = 1,  /* label pass then flow pass, state updated in place */
+    PF_KERNEL_FUSED = 2      /* one pass per iteration, state ping-ponged */
+} pf_kernel;
+
+typedef struct {
+    int32_t batch, ndim, nz, ny, nx;
+} pf_grid;
+
+typedef struct {
+    int32_t n_nodes;         /* including the source (node 0) */
+    int32_t n_edges;
+    const int32_t *parent;   /* host [n_edges] */
+    const int32_t *child;    /* host [n_edges] */
+    const double *weight;    /* host [n_edges], or NULL for 1/|parents(child)| */
+} pf_graph;
+
+typedef struct {
+    int32_t iters;           /* iterations to run, >= 0 */
+    float c;                 /* entropic proximal weight, > 0 */
+    float tau;               /* flow step parameter, > 0 (the step is c*tau) */
+    int32_t storage;         /* pf_storage of the label and flow state */
+    int32_t kernel;          /* pf_kernel */
+    int32_t warm_start;      /* 1: continue from the state in the workspace */
+    int32_t gap_every;       /* > 0: evaluate energy/dual every gap_every iterations */
+    double gap_tol;          /* > 0: stop once (E - P) <= gap_tol * |E| at an evaluation */
+    int32_t final_energy;    /* 1: evaluate energy, dual and gap after the last iteration */
+    int32_t check_inputs;    /* 1: reject NaN/Inf in D and NaN/Inf/negative S first */
+    int32_t timing_stride;   /* > 0: time every timing_stride-th iteration with HIP events */
+    void *workspace;         /* device, 256-byte aligned, caller-owned */
+    size_t workspace_bytes;
+} pf_params;
+
+typedef struct {
+    float *u;                /* device out [B][n_leaf][Z][Y][X] fp32, or NULL */
+    int32_t *labels;         /* device out [B][Z][Y][X] argmax leaf (ties: lowest), or NULL */
+    float *q;                /* device out [B][n_node][ndim][Z][Y][X] fp32, or NULL */
+    double *gap_history;     /* host out [gap_history_cap] absolute gaps, or NULL */
+    int32_t gap_history_cap;
+    /* filled by the call */
+    int32_t gap_history_len;
+    int32_t iters_done;
+    double energy;           /* primal energy E(u), summed over the batch (fp64) */
+    double dual;             /* pseudo-flow dual P(q), summed over the batch (fp64) */
+    double gap;              /* E - P */
+    double max_simplex_err;  /* max over voxels of |sum_L u_L - 1| */
+    double max_flow_excess;  /* max over flows and voxels of |q_A| - S_A (<= 0 if feasible) */
+    double kernel_ms;        /* summed duration of the timed iterations */
+    int32_t kernel_timed;    /* number of timed iterations */
+} pf_result;
+
+/* Bytes of device workspace needed for a problem.  n_leaf end-labels and
+ * n_node non-source nodes carrying a flow (Potts: both equal the label count;
+ * Ishikawa with N+1 labels: n_leaf = N+1, n_node = N).  `params` selects the
+ * storage type and kernel; only those two fields are read.  Returns 0 for
+ * arguments no solver accepts. */
+size_t pf_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t n_node,
+                          const pf_params *params);
+
+/* Pseudo-flow Potts model (Algorithm 1, Potts section: relaxed Potts energy,
+ * pseudo-flow dual max_{|q_L|<=S_L} sum_x min_L (D_L + div q_L), closed-form
+ * entropic label update and the Chambolle flow update).  One iteration is
+ *   d_L  = D_L + div q_L
+ *   u_L <- u_L exp(-d_L/c) / sum_L' u_L' exp(-d_L'/c)   (max-subtracted log-sum-exp)
+ *   q_L <- Proj_{|q_L| <= S_L}(q_L - c tau grad u_L)
+ * starting from u = 1/n_labels, q = 0.  D: device float[B][n_labels][Z][Y][X].
+ * S: per s_mode with n_node = n_labels. */
+int solve_potts(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
+                int32_t s_mode, const pf_params *params, pf_result *result, void *stream);
+
+/* Pseudo-flow DAGMF model (Algorithm 2, DAGMF section): top-down flow excess
+ *   d_A = div q_A + sum_{P in parents(A), P != source} w_(P,A) d_P  (+ D_A at leaves),
+ * the entropic label update over the end-labels, and bottom-up implicit labels
+ *   U_A = sum_{C in children(A)} w_(A,C) U_C  (U = u at leaves)
+ * driving q_A <- Proj_{|q_A| <= S_A}(q_A - c tau grad U_A) for every non-source
+ * node A.  D: device float[B][n_leaf][Z][Y][X]; S per s_mode with n_node =
+ * n_nodes - 1, flow A-1 belonging to node A. */
+int solve_dagmf(const pf_grid *grid, const pf_graph *graph, const float *D, const float *S,
+                int32_t s_mode, const pf_params *params, pf_result *result, void *stream);
+
+/* Hierarchical max-flow: solve_dagmf restricted to trees (every non-source
+ * node has exactly one parent, unit weights), the HMF special case of the
+ * DAGMF section.  A graph that is not such a tree returns PF_EGRAPH. */
+int solve_hmf(const pf_grid *grid, const pf_graph *graph, const float *D, const float *S,
+              int32_t s_mode, const pf_params *params, pf_result *result, void *stream);
+
+/* Pseudo-flow Ishikawa chain (Algorithm 3): labels L_0..L_N (n_labels = N+1),
+ * flows q_1..q_N; flow excess d_i = D_i + sum_{j<=i} div q_j and the flow of
+ * L_i driven by U_i = sum_{j>=i} u_j.  D: device float[B][N+1][Z][Y][X];
+ * S per s_mode with n_node = N.  Supports PF_KERNEL_TWO_PASS/AUTO. */
+int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
+                   int32_t s_mode, const pf_params *params, pf_result *result, void *stream);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *pf_last_error(void);
+
+/* PF_ABI_VERSION of the loaded library. */
+int32_t pf_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSEUDOFLOW_H */

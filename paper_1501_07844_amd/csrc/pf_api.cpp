@@ -1,0 +1,497 @@
+// Host side of the C ABI declared in pseudoflow.h: argument and label-graph
+// validation, path-weight packing, workspace layout, the iteration loop with
+// optional gap evaluations, export and timing.  All device work is enqueued
+// through the launchers of pf_kernels.hip; nothing here allocates device
+// memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pf_internal.h"
+#include "pseudoflow.h"
+
+namespace pf {
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout make_layout(const pf_grid &g, int nl, int nn, int storage, bool pingpong) {
+    Layout L{};
+    const size_t V = (size_t)g.nx * g.ny * g.nz;
+    const size_t s = storage_bytes(storage);
+    size_t off = 0;
+    L.results = off;
+    off += 256;
+    L.flags = off;
+    off += 256;
+    L.consts = off;
+    off = align256(off + sizeof(ConstBlock));
+    L.partials = off;
+    off = align256(off + (size_t)kPartials * 4 * sizeof(double));
+    const size_t ell_b = align256((size_t)g.batch * nl * V * s);
+    const size_t q_b = align256((size_t)g.batch * nn * g.ndim * V * s);
+    L.ell[0] = off;
+    off += ell_b;
+    L.q[0] = off;
+    off += q_b;
+    if (pingpong) {
+        L.ell[1] = off;
+        off += ell_b;
+        L.q[1] = off;
+        off += q_b;
+    } else {
+        L.ell[1] = L.ell[0];
+        L.q[1] = L.q[0];
+    }
+    L.total = off;
+    return L;
+}
+
+}  // namespace pf
+
+using namespace pf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(PF_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// A validated problem, ready to launch.
+struct Prob {
+    pf_grid g{};
+    int nl = 0, nn = 0;
+    const float *D = nullptr;
+    const float *S = nullptr;
+    int s_mode = 0;
+    bool ident = true;
+    GraphW w{};
+    float s_node[PF_MAX_NODES] = {};
+};
+
+int check_grid(const pf_grid *g) {
+    if (!g) return fail(PF_EINVAL, "grid is NULL");
+    if (g->ndim != 2 && g->ndim != 3) return fail(PF_EINVAL, "ndim must be 2 or 3 (got %d)", g->ndim);
+    if (g->batch < 1 || g->nx < 1 || g->ny < 1 || g->nz < 1)
+        return fail(PF_EINVAL, "grid extents must be >= 1 (batch %d, %d x %d x %d)", g->batch,
+                    g->nz, g->ny, g->nx);
+    if (g->ndim == 2 && g->nz != 1) return fail(PF_EINVAL, "ndim == 2 requires nz == 1 (got %d)", g->nz);
+    if (g->batch > 65535) return fail(PF_EUNSUPPORTED, "batch > 65535");
+    const double V = (double)g->nx * g->ny * g->nz;
+    if (V > 2147483647.0 - 2.0 * g->nx * g->ny)
+        return fail(PF_EUNSUPPORTED, "more than 2^31 voxels per problem");
+    return PF_OK;
+}
+
+int check_inputs_common(Prob &p, const float *D, const float *S, int s_mode) {
+    if (!D) return fail(PF_EINVAL, "D is NULL");
+    if (!aligned(D, 4)) return fail(PF_EINVAL, "D is not 4-byte aligned");
+    if (s_mode < PF_S_NODE_SCALAR || s_mode > PF_S_NODE_FIELD)
+        return fail(PF_EINVAL, "unknown s_mode %d", s_mode);
+    if (!S) return fail(PF_EINVAL, "S is NULL");
+    p.D = D;
+    p.s_mode = s_mode;
+    if (s_mode == PF_S_NODE_SCALAR) {
+        for (int A = 0; A < p.nn; ++A) {
+            const float s = S[A];
+            if (!std::isfinite(s)) return fail(PF_ENONFINITE, "S[%d] is not finite", A);
+            if (s < 0.f) return fail(PF_EINVAL, "S[%d] = %g is negative", A, (double)s);
+            p.s_node[A] = s;
+        }
+        p.S = nullptr;
+    } else {
+        if (!aligned(S, 4)) return fail(PF_EINVAL, "S is not 4-byte aligned");
+        p.S = S;
+    }
+    return PF_OK;
+}
+
+int check_params(const pf_params *P) {
+    if (!P) return fail(PF_EINVAL, "params is NULL");
+    if (P->iters < 0) return fail(PF_EINVAL, "iters must be >= 0 (got %d)", P->iters);
+    if (!(P->c > 0.f) || !std::isfinite(P->c)) return fail(PF_EINVAL, "c must be finite and > 0");
+    if (!(P->tau > 0.f) || !std::isfinite(P->tau))
+        return fail(PF_EINVAL, "tau must be finite and > 0");
+    if (P->storage < PF_FP32 || P->storage > PF_FP16)
+        return fail(PF_EINVAL, "unknown storage %d", P->storage);
+    if (P->kernel < PF_KERNEL_AUTO || P->kernel > PF_KERNEL_FUSED)
+        return fail(PF_EINVAL, "unknown kernel %d", P->kernel);
+    if (P->gap_every < 0) return fail(PF_EINVAL, "gap_every must be >= 0");
+    if (!(P->gap_tol >= 0.0)) return fail(PF_EINVAL, "gap_tol must be >= 0");
+    if (P->timing_stride < 0) return fail(PF_EINVAL, "timing_stride must be >= 0");
+    if (!P->workspace) return fail(PF_EINVAL, "workspace is NULL");
+    if (!aligned(P->workspace, 256)) return fail(PF_EINVAL, "workspace is not 256-byte aligned");
+    return PF_OK;
+}
+
+// Label graph -> path weights W[A][L]; checks acyclicity, reachability,
+// weights and the unit source-to-leaf path sums.
+int build_graph(const pf_graph *G, bool tree_only, Prob &p) {
+    if (!G) return fail(PF_EINVAL, "graph is NULL");
+    const int n = G->n_nodes, m = G->n_edges;
+    if (n < 2) return fail(PF_EGRAPH, "graph needs a source and at least one label (n_nodes=%d)", n);
+    if (n - 1 > PF_MAX_NODES)
+        return fail(PF_EUNSUPPORTED, "%d non-source nodes > %d", n - 1, PF_MAX_NODES);
+    if (m < 1 || !G->parent || !G->child) return fail(PF_EGRAPH, "graph has no edges");
+    std::vector<std::vector<int>> ch(n), pa(n);
+    std::vector<std::vector<double>> chw(n);
+    for (int e = 0; e < m; ++e) {
+        const int a = G->parent[e], b = G->child[e];
+        if (a < 0 || a >= n || b < 0 || b >= n)
+            return fail(PF_EGRAPH, "edge %d (%d->%d) names a node outside 0..%d", e, a, b, n - 1);
+        if (a == b) return fail(PF_EGRAPH, "edge %d is a self loop on %d", e, a);
+        if (b == 0) return fail(PF_EGRAPH, "edge %d points into the source", e);
+        if (std::find(ch[a].begin(), ch[a].end(), b) != ch[a].end())
+            return fail(PF_EGRAPH, "duplicate edge %d->%d", a, b);
+        ch[a].push_back(b);
+        pa[b].push_back(a);
+    }
+    for (int e = 0; e < m; ++e) {
+        const int a = G->parent[e], b = G->child[e];
+        double w = 1.0 / (double)pa[b].size();
+        if (G->weight) {
+            w = G->weight[e];
+            if (!std::isfinite(w) || !(w > 0.0))
+                return fail(PF_EGRAPH, "edge %d->%d has weight %g (must be > 0)", a, b, w);
+        }
+        chw[a].push_back(w);
+        (void)b;
+    }
+    for (int b = 1; b < n; ++b)
+        if (pa[b].empty()) return fail(PF_EGRAPH, "node %d has no parent (unreachable)", b);
+    if (tree_only) {
+        for (int b = 1; b < n; ++b)
+            if (pa[b].size() != 1) return fail(PF_EGRAPH, "node %d has %zu parents: not a tree", b, pa[b].size());
+        if (G->weight)
+            for (int e = 0; e < m; ++e)
+                if (G->weight[e] != 1.0) return fail(PF_EGRAPH, "tree edge %d has weight != 1", e);
+    }
+    // Kahn's algorithm
+    std::vector<int> indeg(n), order;
+    for (int b = 0; b < n; ++b) indeg[b] = (int)pa[b].size();
+    std::vector<int> ready;
+    for (int b = 0; b < n; ++b)
+        if (!indeg[b]) ready.push_back(b);
+    while (!ready.empty()) {
+        const int a = ready.back();
+        ready.pop_back();
+        order.push_back(a);
+        for (int c : ch[a])
+            if (--indeg[c] == 0) ready.push_back(c);
+    }
+    if ((int)order.size() != n) return fail(PF_EGRAPH, "label graph has a cycle");
+    std::vector<int> leaves;
+    for (int a = 1; a < n; ++a)
+        if (ch[a].empty()) leaves.push_back(a);
+    if ((int)leaves.size() > PF_MAX_LEAVES)
+        return fail(PF_EUNSUPPORTED, "%zu end-labels > %d", leaves.size(), PF_MAX_LEAVES);
+    // W[a][leaf] by reverse topological order
+    std::vector<std::vector<double>> W(n, std::vector<double>(leaves.size(), 0.0));
+    for (int i = n - 1; i >= 0; --i) {
+        const int a = order[i];
+        if (ch[a].empty()) {
+            const auto it = std::find(leaves.begin(), leaves.end(), a);
+            if (it != leaves.end()) W[a][it - leaves.begin()] = 1.0;
+            continue;
+        }
+        for (size_t j = 0; j < ch[a].size(); ++j)
+            for (size_t L = 0; L < leaves.size(); ++L) W[a][L] += chw[a][j] * W[ch[a][j]][L];
+    }
+    for (size_t L = 0; L < leaves.size(); ++L)
+        if (std::fabs(W[0][L] - 1.0) > 1e-9)
+            return fail(PF_EGRAPH, "path weights from the source to leaf %d sum to %.12g, not 1",
+                        leaves[L], W[0][L]);
+    p.nl = (int)leaves.size();
+    p.nn = n - 1;
+    p.ident = false;
+    std::memset(&p.w, 0, sizeof p.w);
+    p.w.nl = p.nl;
+    p.w.nn = p.nn;
+    for (int A = 1; A < n; ++A)
+        for (int L = 0; L < p.nl; ++L) p.w.w[A - 1][L] = (float)W[A][L];
+    return PF_OK;
+}
+
+struct Timer {
+    std::vector<hipEvent_t> ev;
+    ~Timer() {
+        for (auto e : ev) hipEventDestroy(e);
+    }
+};
+
+int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
+    const bool want_fused = P->kernel == PF_KERNEL_FUSED ||
+                            (P->kernel == PF_KERNEL_AUTO &&
+                             fused_supported(p.g.ndim, p.nl, p.nn, p.ident));
+    if (P->kernel == PF_KERNEL_FUSED && !fused_supported(p.g.ndim, p.nl, p.nn, p.ident))
+        return fail(PF_EUNSUPPORTED, "fused kernel unavailable for this problem");
+    const Layout lay = make_layout(p.g, p.nl, p.nn, P->storage, want_fused);
+    if (P->workspace_bytes < lay.total)
+        return fail(PF_ENOMEM, "workspace of %zu bytes < %zu needed", P->workspace_bytes, lay.total);
+    if (!R) return fail(PF_EINVAL, "result is NULL");
+    if ((R->u && !aligned(R->u, 4)) || (R->labels && !aligned(R->labels, 4)) ||
+        (R->q && !aligned(R->q, 4)))
+        return fail(PF_EINVAL, "output pointers must be 4-byte aligned");
+    if (R->gap_history && R->gap_history_cap < 0) return fail(PF_EINVAL, "gap_history_cap < 0");
+
+    char *ws = static_cast<char *>(P->workspace);
+    double *results = reinterpret_cast<double *>(ws + lay.results);
+    int32_t *flags = reinterpret_cast<int32_t *>(ws + lay.flags);
+    double *partials = reinterpret_cast<double *>(ws + lay.partials);
+    void *ell[2] = {ws + lay.ell[0], ws + lay.ell[1]};
+    void *q[2] = {ws + lay.q[0], ws + lay.q[1]};
+    float *consts = reinterpret_cast<float *>(ws + lay.consts);
+    const int nd = p.g.ndim;
+    const bool ident = p.ident;
+
+    StepArgs a{};
+    a.nx = p.g.nx;
+    a.ny = p.g.ny;
+    a.nz = p.g.nz;
+    a.V = p.g.nx * p.g.ny * p.g.nz;
+    a.B = p.g.batch;
+    a.nl = p.nl;
+    a.nn = p.nn;
+    a.inv_c = 1.0f / P->c;
+    a.ctau = P->c * P->tau;
+    a.s_mode = p.s_mode;
+    a.D = p.D;
+    a.S = p.S;
+    a.s_node = consts;
+    a.W = consts + PF_MAX_NODES;
+    a.ell_in = a.ell_out = ell[0];
+    a.q_in = a.q_out = q[0];
+
+    R->iters_done = 0;
+    R->gap_history_len = 0;
+    R->energy = R->dual = R->gap = NAN;
+    R->max_simplex_err = R->max_flow_excess = NAN;
+    R->kernel_ms = 0.0;
+    R->kernel_timed = 0;
+
+    hipError_t e;
+    {
+        ConstBlock cb{};
+        std::memcpy(cb.s_node, p.s_node, sizeof cb.s_node);
+        for (int A = 0; A < PF_MAX_NODES; ++A)
+            for (int L = 0; L < PF_MAX_LEAVES; ++L) cb.w[A * PF_MAX_LEAVES + L] = p.w.w[A][L];
+        if ((e = launch_upload(cb, consts, stream)) != hipSuccess) return hip_fail(e, "upload");
+    }
+    if (P->check_inputs) {
+        if ((e = launch_check(a, flags, stream)) != hipSuccess) return hip_fail(e, "input check");
+        int32_t flag = 0;
+        if ((e = hipMemcpyAsync(&flag, flags, sizeof flag, hipMemcpyDeviceToHost, stream)) != hipSuccess)
+            return hip_fail(e, "input check copy");
+        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "input check sync");
+        if (flag & 1) return fail(PF_ENONFINITE, "D holds NaN or Inf");
+        if (flag & 2) return fail(PF_ENONFINITE, "S holds NaN, Inf or a negative value");
+    }
+    if (!P->warm_start) {
+        if ((e = launch_init(a, nd, P->storage, -logf((float)p.nl), stream)) != hipSuccess)
+            return hip_fail(e, "init");
+    }
+
+    auto evaluate = [&](double out[4]) -> int {
+        hipError_t err = launch_energy(a, ident, nd, P->storage, partials, results, stream);
+        if (err != hipSuccess) return hip_fail(err, "energy");
+        if ((err = hipMemcpyAsync(out, results, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                                  stream)) != hipSuccess)
+            return hip_fail(err, "energy copy");
+        if ((err = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(err, "energy sync");
+        if (!std::isfinite(out[0]) || !std::isfinite(out[1]))
+            return fail(PF_ENONFINITE, "non-finite energy/dual after %d iterations", R->iters_done);
+        return PF_OK;
+    };
+
+    Timer timer;
+    int cur = 0;
+    for (int it = 0; it < P->iters; ++it) {
+        const bool timed = P->timing_stride > 0 && it % P->timing_stride == 0;
+        if (timed) {
+            hipEvent_t e0, e1;
+            if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+                return fail(PF_EHIP, "hipEventCreate failed");
+            timer.ev.push_back(e0);
+            timer.ev.push_back(e1);
+            hipEventRecord(e0, stream);
+        }
+        if (want_fused) {
+            a.ell_in = ell[cur];
+            a.q_in = q[cur];
+            a.ell_out = ell[1 - cur];
+            a.q_out = q[1 - cur];
+            if ((e = launch_fused(a, ident, nd, P->storage, stream)) != hipSuccess)
+                return hip_fail(e, "fused step");
+            cur = 1 - cur;
+            a.ell_in = a.ell_out;
+            a.q_in = a.q_out;
+        } else {
+            if ((e = launch_label(a, ident, nd, P->storage, stream)) != hipSuccess)
+                return hip_fail(e, "label pass");
+            if ((e = launch_flow(a, ident, nd, P->storage, stream)) != hipSuccess)
+                return hip_fail(e, "flow pass");
+        }
+        if (timed) hipEventRecord(timer.ev.back(), stream);
+        R->iters_done = it + 1;
+        if (P->gap_every > 0 && (it + 1) % P->gap_every == 0) {
+            double r[4];
+            const int st = evaluate(r);
+            if (st != PF_OK) return st;
+            const double gap = r[0] - r[1];
+            if (R->gap_history && R->gap_history_len < R->gap_history_cap)
+                R->gap_history[R->gap_history_len++] = gap;
+            R->energy = r[0];
+            R->dual = r[1];
+            R->gap = gap;
+            R->max_simplex_err = r[2];
+            R->max_flow_excess = r[3];
+            if (P->gap_tol > 0.0 && gap <= P->gap_tol * std::fabs(r[0])) break;
+        }
+    }
+    if (cur == 1) {
+        // bring the state back to the first buffer so that a warm start finds it
+        StepArgs c = a;
+        c.ell_in = ell[1];
+        c.q_in = q[1];
+        c.ell_out = ell[0];
+        c.q_out = q[0];
+        if ((e = launch_copy_state(c, nd, P->storage, stream)) != hipSuccess)
+            return hip_fail(e, "state copy");
+        a.ell_in = a.ell_out = ell[0];
+        a.q_in = a.q_out = q[0];
+    }
+    if (P->final_energy) {
+        double r[4];
+        const int st = evaluate(r);
+        if (st != PF_OK) return st;
+        R->energy = r[0];
+        R->dual = r[1];
+        R->gap = r[0] - r[1];
+        R->max_simplex_err = r[2];
+        R->max_flow_excess = r[3];
+    }
+    if (R->u || R->labels || R->q) {
+        if ((e = launch_export(a, nd, P->storage, R->u, R->labels, R->q, stream)) != hipSuccess)
+            return hip_fail(e, "export");
+    }
+    if (!timer.ev.empty()) {
+        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "timing sync");
+        double ms = 0.0;
+        for (size_t i = 0; i + 1 < timer.ev.size(); i += 2) {
+            float t = 0.f;
+            if ((e = hipEventElapsedTime(&t, timer.ev[i], timer.ev[i + 1])) != hipSuccess)
+                return hip_fail(e, "hipEventElapsedTime");
+            ms += t;
+        }
+        R->kernel_ms = ms;
+        R->kernel_timed = (int)(timer.ev.size() / 2);
+    }
+    g_err.clear();
+    return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pf_abi_version(void) { return PF_ABI_VERSION; }
+
+const char *pf_last_error(void) { return g_err.c_str(); }
+
+size_t pf_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t n_node,
+                          const pf_params *params) {
+    if (check_grid(grid) != PF_OK || !params) return 0;
+    if (n_leaf < 1 || n_leaf > PF_MAX_LEAVES || n_node < 1 || n_node > PF_MAX_NODES) return 0;
+    if (params->storage < PF_FP32 || params->storage > PF_FP16) return 0;
+    // the same sizes serve the identity (Potts) and weighted families
+    const bool fused = params->kernel == PF_KERNEL_FUSED ||
+                       (params->kernel == PF_KERNEL_AUTO &&
+                        (fused_supported(grid->ndim, n_leaf, n_node, true) ||
+                         fused_supported(grid->ndim, n_leaf, n_node, false)));
+    return make_layout(*grid, n_leaf, n_node, params->storage, fused).total;
+}
+
+int solve_potts(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
+                int32_t s_mode, const pf_params *params, pf_result *result, void *stream) {
+    int st;
+    if ((st = check_grid(grid)) != PF_OK) return st;
+    if ((st = check_params(params)) != PF_OK) return st;
+    if (n_labels < 1) return fail(PF_EINVAL, "n_labels must be >= 1");
+    if (n_labels > PF_MAX_LEAVES) return fail(PF_EUNSUPPORTED, "n_labels > %d", PF_MAX_LEAVES);
+    Prob p;
+    p.g = *grid;
+    p.nl = p.nn = n_labels;
+    p.ident = true;
+    if ((st = check_inputs_common(p, D, S, s_mode)) != PF_OK) return st;
+    return run(p, params, result, static_cast<hipStream_t>(stream));
+}
+
+static int solve_graph(const pf_grid *grid, const pf_graph *graph, bool tree, const float *D,
+                       const float *S, int32_t s_mode, const pf_params *params,
+                       pf_result *result, void *stream) {
+    int st;
+    if ((st = check_grid(grid)) != PF_OK) return st;
+    if ((st = check_params(params)) != PF_OK) return st;
+    Prob p;
+    p.g = *grid;
+    if ((st = build_graph(graph, tree, p)) != PF_OK) return st;
+    if ((st = check_inputs_common(p, D, S, s_mode)) != PF_OK) return st;
+    return run(p, params, result, static_cast<hipStream_t>(stream));
+}
+
+int solve_dagmf(const pf_grid *grid, const pf_graph *graph, const float *D, const float *S,
+                int32_t s_mode, const pf_params *params, pf_result *result, void *stream) {
+    return solve_graph(grid, graph, false, D, S, s_mode, params, result, stream);
+}
+
+int solve_hmf(const pf_grid *grid, const pf_graph *graph, const float *D, const float *S,
+              int32_t s_mode, const pf_params *params, pf_result *result, void *stream) {
+    return solve_graph(grid, graph, true, D, S, s_mode, params, result, stream);
+}
+
+int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
+                   int32_t s_mode, const pf_params *params, pf_result *result, void *stream) {
+    int st;
+    if ((st = check_grid(grid)) != PF_OK) return st;
+    if ((st = check_params(params)) != PF_OK) return st;
+    if (n_labels < 2) return fail(PF_EINVAL, "the Ishikawa chain needs n_labels >= 2");
+    if (n_labels > PF_MAX_LEAVES) return fail(PF_EUNSUPPORTED, "n_labels > %d", PF_MAX_LEAVES);
+    if (params->kernel == PF_KERNEL_FUSED)
+        return fail(PF_EUNSUPPORTED, "no fused kernel for the Ishikawa chain");
+    Prob p;
+    p.g = *grid;
+    p.nl = n_labels;
+    p.nn = n_labels - 1;
+    p.ident = false;
+    std::memset(&p.w, 0, sizeof p.w);
+    p.w.nl = p.nl;
+    p.w.nn = p.nn;
+    // flow j (of label L_{j+1}) drives every label L_i with i >= j + 1
+    for (int j = 0; j < p.nn; ++j)
+        for (int L = j + 1; L < p.nl; ++L) p.w.w[j][L] = 1.0f;
+    if ((st = check_inputs_common(p, D, S, s_mode)) != PF_OK) return st;
+    pf_params P2 = *params;
+    P2.kernel = PF_KERNEL_TWO_PASS;
+    return run(p, &P2, result, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// Internal interface between the C-ABI host code (pf_api.cpp) and the gfx950
+// kernels (pf_kernels.hip).  Not installed; the public ABI is pseudoflow.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "pseudoflow.h"
+
+namespace pf {
+
+// Label-graph coupling in path-weight form.  Node A (0-based over the
+// non-source nodes) and end-label L are linked by W[A][L], the sum over the
+// paths A -> L of the products of edge weights (W = 1 on the diagonal of a
+// leaf).  With it the top-down flow excess is d_L = D_L + sum_A W[A][L] div q_A
+// and the bottom-up implicit label is U_A = sum_L W[A][L] u_L.
+struct GraphW {
+    int32_t nl, nn;
+    float w[PF_MAX_NODES][PF_MAX_LEAVES];
+};
+
+// Per-solve constants copied into the workspace before the first launch:
+// the node capacities of PF_S_NODE_SCALAR and the path weights.
+struct ConstBlock {
+    float s_node[PF_MAX_NODES];
+    float w[PF_MAX_NODES * PF_MAX_LEAVES];
+};
+constexpr int kConstFloats = PF_MAX_NODES + PF_MAX_NODES * PF_MAX_LEAVES;
+
+// Arguments common to every per-iteration kernel.
+struct StepArgs {
+    int32_t nx, ny, nz;      // grid extents (nz == 1 in 2-D)
+    int32_t V;               // voxels per problem
+    int32_t B;               // problems
+    int32_t nl, nn;          // end-labels, flows
+    float inv_c;             // 1/c
+    float ctau;              // c * tau
+    int32_t s_mode;          // pf_s_mode
+    const float *D;          // [B][nl][V]
+    const float *S;          // field (shared or per node) or null
+    const float *s_node;     // workspace copy of ConstBlock::s_node
+    const float *W;          // workspace copy of ConstBlock::w, [A * PF_MAX_LEAVES + L]
+    const void *ell_in;      // storage [B][nl][V]
+    const void *q_in;        // storage [B][nn][nd][V]
+    void *ell_out;           // == ell_in for in-place passes
+    void *q_out;
+};
+
+// Workspace partition (byte offsets from the workspace base).
+struct Layout {
+    size_t results;          // 8 doubles: E, P, simplex err, flow excess, ...
+    size_t flags;            // 64 int32
+    size_t consts;           // ConstBlock
+    size_t partials;         // kPartials x 4 doubles
+    size_t ell[2];           // label state, ping and pong
+    size_t q[2];             // flow state, ping and pong
+    size_t total;
+};
+
+constexpr int kPartials = 1024;
+constexpr int kBlock = 256;
+
+size_t storage_bytes(int storage);
+Layout make_layout(const pf_grid &g, int nl, int nn, int storage, bool pingpong);
+
+// Launchers; return hipSuccess or the launch error.
+hipError_t launch_upload(const ConstBlock &c, float *dst, hipStream_t s);
+hipError_t launch_init(const StepArgs &a, int nd, int storage, float ell0, hipStream_t s);
+hipError_t launch_label(const StepArgs &a, bool ident, int nd, int storage, hipStream_t s);
+hipError_t launch_flow(const StepArgs &a, bool ident, int nd, int storage, hipStream_t s);
+hipError_t launch_fused(const StepArgs &a, bool ident, int nd, int storage, hipStream_t s);
+bool fused_supported(int nd, int nl, int nn, bool identity);
+hipError_t launch_copy_state(const StepArgs &a, int nd, int storage, hipStream_t s);
+hipError_t launch_energy(const StepArgs &a, bool ident, int nd, int storage,
+                         double *partials, double *results, hipStream_t s);
+hipError_t launch_export(const StepArgs &a, int nd, int storage, float *u, int32_t *labels,
+                         float *q, hipStream_t s);
+hipError_t launch_check(const StepArgs &a, int32_t *flag, hipStream_t s);
+
+}  // namespace pf

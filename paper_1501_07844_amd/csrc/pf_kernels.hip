@@ -1,0 +1,609 @@
+// gfx950 kernels of the pseudo-flow continuous max-flow iteration.
+//
+// One iteration (Algorithm 1 for Potts, Algorithm 2 for DAGMF/HMF,
+// Algorithm 3 for the Ishikawa chain) in path-weight form:
+//   label pass:  d_L = D_L + sum_A W[A][L] div q_A           (top-down excess)
+//                ell_L <- ell_L - d_L/c - LSE_L'(ell_L' - d_L'/c)   (proximal step)
+//   flow pass:   grad U_A = sum_L W[A][L] grad u_L,  u = exp(ell)  (bottom-up labels)
+//                q_A <- Proj_{|q_A| <= S_A}(q_A - c tau grad U_A)  (Chambolle step)
+// Potts is W = identity and is compiled as its own specialisation.
+//
+// State is stored as ell = ln u (float32, bfloat16 or float16) and flows in
+// the same type; all arithmetic is float32; energy/dual reductions are float64.
+// The path is HBM-bandwidth bound (about one flop per byte), so there is no
+// matrix-core work: one voxel per lane, x fastest, every field read and
+// written with unit stride across the wavefront.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "pf_internal.h"
+
+namespace pf {
+namespace {
+
+// ------------------------------------------------------------ storage ----
+
+struct bf16s {
+    uint16_t b;
+};
+using f16s = _Float16;
+
+__device__ __forceinline__ float ld(const float *p, size_t i) { return p[i]; }
+__device__ __forceinline__ float ld(const bf16s *p, size_t i) {
+    return __uint_as_float(uint32_t(p[i].b) << 16);
+}
+__device__ __forceinline__ float ld(const f16s *p, size_t i) { return (float)p[i]; }
+
+__device__ __forceinline__ void st(float *p, size_t i, float v) { p[i] = v; }
+__device__ __forceinline__ void st(bf16s *p, size_t i, float v) {
+    // round to nearest even; NaN stays a quiet NaN
+    uint32_t u = __float_as_uint(v);
+    uint16_t r;
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+        r = uint16_t((u >> 16) | 0x40u);
+    } else {
+        u += 0x7fffu + ((u >> 16) & 1u);
+        r = uint16_t(u >> 16);
+    }
+    p[i].b = r;
+}
+__device__ __forceinline__ void st(f16s *p, size_t i, float v) { p[i] = (f16s)v; }
+
+// Per-solve constants (node capacities, path weights) live in the workspace
+// and are read through the constant address space: uniform across the
+// wavefront and never written by the iteration kernels, so they become
+// scalar loads.
+using cfloat = const __attribute__((address_space(4))) float;
+__device__ __forceinline__ float cld(const float *p, int i) {
+    return ((cfloat *)p)[i];
+}
+__device__ __forceinline__ float wgt(const StepArgs &a, int A, int L) {
+    return cld(a.W, A * PF_MAX_LEAVES + L);
+}
+
+// ------------------------------------------------------------ helpers ----
+
+struct Coord {
+    int x, y, z;
+};
+
+__device__ __forceinline__ Coord coord_of(int v, int nx, int ny) {
+    Coord c;
+    c.x = v % nx;
+    const int r = v / nx;
+    c.y = r % ny;
+    c.z = r / ny;
+    return c;
+}
+
+// S_A at voxel v of problem b.
+__device__ __forceinline__ float smooth(const StepArgs &a, int b, int A, int v) {
+    if (a.s_mode == PF_S_NODE_SCALAR) return cld(a.s_node, A);
+    if (a.s_mode == PF_S_SHARED_FIELD) return a.S[(size_t)b * a.V + v];
+    return a.S[((size_t)b * a.nn + A) * a.V + v];
+}
+
+// div q_A at (c, v): sum_k q_k(x)[x_k < N_k - 1] - q_k(x - e_k)[x_k > 0].
+template <int ND, typename T>
+__device__ __forceinline__ float divergence(const T *qa, size_t V, int v, const Coord &c,
+                                            const StepArgs &a) {
+    float dv = 0.f;
+    if (c.x < a.nx - 1) dv += ld(qa, v);
+    if (c.x > 0) dv -= ld(qa, v - 1);
+    const T *qy = qa + V;
+    if (c.y < a.ny - 1) dv += ld(qy, v);
+    if (c.y > 0) dv -= ld(qy, v - a.nx);
+    if constexpr (ND == 3) {
+        const T *qz = qa + 2 * V;
+        const int sz = a.nx * a.ny;
+        if (c.z < a.nz - 1) dv += ld(qz, v);
+        if (c.z > 0) dv -= ld(qz, v - sz);
+    }
+    return dv;
+}
+
+// --------------------------------------------------------- label pass ----
+
+template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
+__device__ __forceinline__ void label_body(const StepArgs &a) {
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= a.V) return;
+    const int b = blockIdx.y;
+    const Coord c = coord_of(v, a.nx, a.ny);
+    const size_t V = (size_t)a.V;
+    const T *q = static_cast<const T *>(a.q_in);
+    const T *ell = static_cast<const T *>(a.ell_in);
+    T *out = static_cast<T *>(a.ell_out);
+
+    float d[NLMAX];
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L)
+        if (L < a.nl) d[L] = a.D[((size_t)b * a.nl + L) * V + v];
+#pragma unroll
+    for (int A = 0; A < NNMAX; ++A) {
+        if (A < a.nn) {
+            const T *qa = q + ((size_t)b * a.nn + A) * ND * V;
+            const float dv = divergence<ND>(qa, V, v, c, a);
+            if constexpr (IDENT) {
+                d[A] += dv;
+            } else {
+#pragma unroll
+                for (int L = 0; L < NLMAX; ++L) {
+                    if (L < a.nl) {
+                        const float w = wgt(a, A, L);
+                        if (w != 0.f) d[L] = fmaf(w, dv, d[L]);
+                    }
+                }
+            }
+        }
+    }
+    // entropic proximal step, max-subtracted log-sum-exp in the log domain
+    float t[NLMAX];
+    float m = -INFINITY;
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L) {
+        if (L < a.nl) {
+            t[L] = fmaf(-d[L], a.inv_c, ld(ell, ((size_t)b * a.nl + L) * V + v));
+            m = fmaxf(m, t[L]);
+        }
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L)
+        if (L < a.nl) s += __expf(t[L] - m);
+    const float ls = __logf(s);
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L)
+        if (L < a.nl) st(out, ((size_t)b * a.nl + L) * V + v, (t[L] - m) - ls);
+}
+
+template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
+__global__ __launch_bounds__(kBlock) void k_label(StepArgs a) {
+    label_body<ND, NLMAX, NNMAX, IDENT, T>(a);
+}
+
+// ---------------------------------------------------------- flow pass ----
+
+// Gradient step and projection of flow A at voxel v given grad U_A.
+template <int ND, typename T>
+__device__ __forceinline__ void flow_update(const StepArgs &a, int b, int A, int v,
+                                            const float (&G)[3], const bool (&h)[3]) {
+    const size_t V = (size_t)a.V;
+    const size_t base = ((size_t)b * a.nn + A) * ND * V + v;
+    const T *qa = static_cast<const T *>(a.q_in) + base;
+    T *qo = static_cast<T *>(a.q_out) + base;
+    float p[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) p[k] = h[k] ? fmaf(-a.ctau, G[k], ld(qa, k * V)) : 0.f;
+    const float S = smooth(a, b, A, v);
+    float n2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) n2 = fmaf(p[k], p[k], n2);
+    if (n2 > S * S) {
+        const float sc = S * rsqrtf(n2);
+#pragma unroll
+        for (int k = 0; k < ND; ++k) p[k] *= sc;
+    }
+#pragma unroll
+    for (int k = 0; k < ND; ++k) st(qo, k * V, p[k]);
+}
+
+template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
+__device__ __forceinline__ void flow_body(const StepArgs &a) {
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= a.V) return;
+    const int b = blockIdx.y;
+    const Coord c = coord_of(v, a.nx, a.ny);
+    const size_t V = (size_t)a.V;
+    const T *ell = static_cast<const T *>(a.ell_in);
+    const bool h[3] = {c.x < a.nx - 1, c.y < a.ny - 1, ND == 3 && c.z < a.nz - 1};
+    const int off[3] = {1, a.nx, a.nx * a.ny};
+
+    if constexpr (IDENT) {
+#pragma unroll
+        for (int L = 0; L < NLMAX; ++L) {
+            if (L < a.nl) {
+                const T *e = ell + ((size_t)b * a.nl + L) * V + v;
+                const float u0 = __expf(ld(e, 0));
+                float G[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                for (int k = 0; k < ND; ++k)
+                    if (h[k]) G[k] = __expf(ld(e, off[k])) - u0;
+                flow_update<ND, T>(a, b, L, v, G, h);
+            }
+        }
+    } else {
+        float gu[NLMAX][ND];
+#pragma unroll
+        for (int L = 0; L < NLMAX; ++L) {
+            if (L < a.nl) {
+                const T *e = ell + ((size_t)b * a.nl + L) * V + v;
+                const float u0 = __expf(ld(e, 0));
+#pragma unroll
+                for (int k = 0; k < ND; ++k) gu[L][k] = h[k] ? __expf(ld(e, off[k])) - u0 : 0.f;
+            }
+        }
+#pragma unroll
+        for (int A = 0; A < NNMAX; ++A) {
+            if (A < a.nn) {
+                float G[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                for (int L = 0; L < NLMAX; ++L) {
+                    if (L < a.nl) {
+                        const float w = wgt(a, A, L);
+                        if (w != 0.f) {
+#pragma unroll
+                            for (int k = 0; k < ND; ++k) G[k] = fmaf(w, gu[L][k], G[k]);
+                        }
+                    }
+                }
+                flow_update<ND, T>(a, b, A, v, G, h);
+            }
+        }
+    }
+}
+
+template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
+__global__ __launch_bounds__(kBlock) void k_flow(StepArgs a) {
+    flow_body<ND, NLMAX, NNMAX, IDENT, T>(a);
+}
+
+// ------------------------------------------------- init / copy / export --
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init(T *ell, size_t n_ell, T *q, size_t n_q,
+                                                 float ell0) {
+    const size_t stride = (size_t)gridDim.x * kBlock;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n_ell; i += stride)
+        st(ell, i, ell0);
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n_q; i += stride)
+        st(q, i, 0.f);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy(const T *__restrict__ a, T *__restrict__ b,
+                                                 size_t n, const T *__restrict__ c,
+                                                 T *__restrict__ d, size_t m) {
+    const size_t stride = (size_t)gridDim.x * kBlock;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) b[i] = a[i];
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) d[i] = c[i];
+}
+
+template <int ND, typename T>
+__global__ __launch_bounds__(kBlock) void k_export(StepArgs a, float *u, int32_t *labels,
+                                                   float *qo) {
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= a.V) return;
+    const int b = blockIdx.y;
+    const size_t V = (size_t)a.V;
+    const T *ell = static_cast<const T *>(a.ell_in);
+    int best = 0;
+    float bv = -INFINITY;
+    for (int L = 0; L < a.nl; ++L) {
+        const size_t i = ((size_t)b * a.nl + L) * V + v;
+        const float e = ld(ell, i);
+        if (u) u[i] = expf(e);
+        if (e > bv) {
+            bv = e;
+            best = L;
+        }
+    }
+    if (labels) labels[(size_t)b * V + v] = best;
+    if (qo) {
+        const T *q = static_cast<const T *>(a.q_in);
+        for (int j = 0; j < a.nn * ND; ++j) {
+            const size_t i = ((size_t)b * a.nn * ND + j) * V + v;
+            qo[i] = ld(q, i);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_check(const float *D, size_t nD, const float *S,
+                                                  size_t nS, int32_t *flag) {
+    const size_t stride = (size_t)gridDim.x * kBlock;
+    int bad = 0;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < nD; i += stride)
+        bad |= !isfinite(D[i]);
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < nS; i += stride)
+        bad |= !(isfinite(S[i]) && S[i] >= 0.f) ? 2 : 0;
+    if (bad) atomicOr(flag, bad);
+}
+
+__global__ __launch_bounds__(kBlock) void k_upload(ConstBlock c, float *dst) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < PF_MAX_NODES) dst[i] = c.s_node[i];
+    else if (i < kConstFloats) dst[i] = c.w[i - PF_MAX_NODES];
+}
+
+__global__ void k_zero_flag(int32_t *flag) {
+    if (threadIdx.x == 0) flag[0] = 0;
+}
+
+// ---------------------------------------------------- energy and dual ----
+
+// Per block: sum of E, sum of P, max |sum u - 1|, max(|q_A| - S_A), in fp64.
+template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
+__device__ __forceinline__ void energy_body(const StepArgs &a, double *partials) {
+    __shared__ double red[4][kBlock];
+    const size_t V = (size_t)a.V;
+    const size_t total = V * a.B;
+    const T *ell = static_cast<const T *>(a.ell_in);
+    const T *q = static_cast<const T *>(a.q_in);
+    double e_sum = 0.0, p_sum = 0.0, mx_s = 0.0, mx_q = -INFINITY;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * kBlock) {
+        const int b = (int)(i / V);
+        const int v = (int)(i - (size_t)b * V);
+        const Coord c = coord_of(v, a.nx, a.ny);
+        const bool h[3] = {c.x < a.nx - 1, c.y < a.ny - 1, ND == 3 && c.z < a.nz - 1};
+        const int off[3] = {1, a.nx, a.nx * a.ny};
+        // labels at x and at the forward neighbours (float32 exp of the stored
+        // state), every product and sum in float64
+        float u[NLMAX], un[NLMAX][ND];
+        double d[NLMAX];
+        double su = 0.0, e = 0.0;
+#pragma unroll
+        for (int L = 0; L < NLMAX; ++L) {
+            if (L < a.nl) {
+                const size_t fi = ((size_t)b * a.nl + L) * V + v;
+                u[L] = expf(ld(ell, fi));
+                su += (double)u[L];
+                d[L] = (double)a.D[fi];
+                e += d[L] * (double)u[L];
+#pragma unroll
+                for (int k = 0; k < ND; ++k) un[L][k] = h[k] ? expf(ld(ell, fi + off[k])) : u[L];
+            }
+        }
+#pragma unroll
+        for (int A = 0; A < NNMAX; ++A) {
+            if (A < a.nn) {
+                double G[ND];
+#pragma unroll
+                for (int k = 0; k < ND; ++k) G[k] = 0.0;
+                if constexpr (IDENT) {
+#pragma unroll
+                    for (int k = 0; k < ND; ++k) G[k] = (double)un[A][k] - (double)u[A];
+                } else {
+#pragma unroll
+                    for (int L = 0; L < NLMAX; ++L) {
+                        if (L < a.nl) {
+                            const double wl = (double)wgt(a, A, L);
+                            if (wl != 0.0) {
+#pragma unroll
+                                for (int k = 0; k < ND; ++k)
+                                    G[k] += wl * ((double)un[L][k] - (double)u[L]);
+                            }
+                        }
+                    }
+                }
+                double n2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < ND; ++k) n2 += G[k] * G[k];
+                const double S = (double)smooth(a, b, A, v);
+                e += S * sqrt(n2);
+                // flow excess over the capacity and divergence, fp64
+                const T *qa = q + ((size_t)b * a.nn + A) * ND * V;
+                double qn2 = 0.0, dv = 0.0;
+                const double qx = ld(qa, v), qy = ld(qa, V + v);
+                qn2 += qx * qx + qy * qy;
+                if (c.x < a.nx - 1) dv += qx;
+                if (c.x > 0) dv -= (double)ld(qa, v - 1);
+                if (c.y < a.ny - 1) dv += qy;
+                if (c.y > 0) dv -= (double)ld(qa, V + v - a.nx);
+                if constexpr (ND == 3) {
+                    const double qz = ld(qa, 2 * V + v);
+                    qn2 += qz * qz;
+                    if (c.z < a.nz - 1) dv += qz;
+                    if (c.z > 0) dv -= (double)ld(qa, 2 * V + v - off[2]);
+                }
+                mx_q = fmax(mx_q, sqrt(qn2) - S);
+                if constexpr (IDENT) {
+                    d[A] += dv;
+                } else {
+#pragma unroll
+                    for (int L = 0; L < NLMAX; ++L)
+                        if (L < a.nl) {
+                            const double wl = (double)wgt(a, A, L);
+                            if (wl != 0.0) d[L] += wl * dv;
+                        }
+                }
+            }
+        }
+        double pm = INFINITY;
+#pragma unroll
+        for (int L = 0; L < NLMAX; ++L)
+            if (L < a.nl) pm = fmin(pm, d[L]);
+        e_sum += e;
+        p_sum += pm;
+        mx_s = fmax(mx_s, fabs(su - 1.0));
+    }
+    red[0][threadIdx.x] = e_sum;
+    red[1][threadIdx.x] = p_sum;
+    red[2][threadIdx.x] = mx_s;
+    red[3][threadIdx.x] = mx_q;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+            red[2][threadIdx.x] = fmax(red[2][threadIdx.x], red[2][threadIdx.x + s]);
+            red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) partials[blockIdx.x * 4 + j] = red[j][0];
+    }
+}
+
+template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
+__global__ __launch_bounds__(kBlock) void k_energy(StepArgs a, double *partials) {
+    energy_body<ND, NLMAX, NNMAX, IDENT, T>(a, partials);
+}
+
+// Fixed-order final reduction of the block partials (deterministic).
+__global__ __launch_bounds__(kBlock) void k_reduce(const double *partials, int n,
+                                                   double *results) {
+    __shared__ double red[4][kBlock];
+    double s0 = 0.0, s1 = 0.0, m2 = 0.0, m3 = -INFINITY;
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+        s0 += partials[i * 4 + 0];
+        s1 += partials[i * 4 + 1];
+        m2 = fmax(m2, partials[i * 4 + 2]);
+        m3 = fmax(m3, partials[i * 4 + 3]);
+    }
+    red[0][threadIdx.x] = s0;
+    red[1][threadIdx.x] = s1;
+    red[2][threadIdx.x] = m2;
+    red[3][threadIdx.x] = m3;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+            red[2][threadIdx.x] = fmax(red[2][threadIdx.x], red[2][threadIdx.x + s]);
+            red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        results[0] = red[0][0];
+        results[1] = red[1][0];
+        results[2] = red[2][0];
+        results[3] = red[3][0];
+    }
+}
+
+// ----------------------------------------------------------- dispatch ----
+
+template <int ND, typename T, typename F>
+hipError_t by_bucket(bool ident, int nl, int nn, F &f) {
+    if (ident) {
+        if (nl <= 4) return f.template operator()<ND, 4, 4, true, T>();
+        if (nl <= 8) return f.template operator()<ND, 8, 8, true, T>();
+        return f.template operator()<ND, 16, 16, true, T>();
+    }
+    if (nl <= 4 && nn <= 8) return f.template operator()<ND, 4, 8, false, T>();
+    if (nl <= 8 && nn <= 16) return f.template operator()<ND, 8, 16, false, T>();
+    return f.template operator()<ND, 16, 32, false, T>();
+}
+
+template <typename F>
+hipError_t dispatch(int nd, int storage, bool ident, int nl, int nn, F &&f) {
+    if (nd == 2) {
+        if (storage == PF_BF16) return by_bucket<2, bf16s>(ident, nl, nn, f);
+        if (storage == PF_FP16) return by_bucket<2, f16s>(ident, nl, nn, f);
+        return by_bucket<2, float>(ident, nl, nn, f);
+    }
+    if (storage == PF_BF16) return by_bucket<3, bf16s>(ident, nl, nn, f);
+    if (storage == PF_FP16) return by_bucket<3, f16s>(ident, nl, nn, f);
+    return by_bucket<3, float>(ident, nl, nn, f);
+}
+
+template <typename F>
+hipError_t dispatch_type(int storage, F &&f) {
+    if (storage == PF_BF16) return f.template operator()<bf16s>();
+    if (storage == PF_FP16) return f.template operator()<f16s>();
+    return f.template operator()<float>();
+}
+
+dim3 voxel_grid(const StepArgs &a) {
+    return dim3((unsigned)((a.V + kBlock - 1) / kBlock), (unsigned)a.B, 1);
+}
+
+unsigned stride_blocks(size_t n) {
+    const size_t b = (n + kBlock - 1) / kBlock;
+    return (unsigned)(b < 4096 ? (b ? b : 1) : 4096);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------- launchers ----
+
+size_t storage_bytes(int storage) { return storage == PF_FP32 ? 4 : 2; }
+
+hipError_t launch_init(const StepArgs &a, int nd, int storage, float ell0, hipStream_t s) {
+    const size_t n_ell = (size_t)a.B * a.nl * a.V;
+    const size_t n_q = (size_t)a.B * a.nn * nd * a.V;
+    return dispatch_type(storage, [&]<typename T>() {
+        k_init<T><<<stride_blocks(n_ell > n_q ? n_ell : n_q), kBlock, 0, s>>>(
+            static_cast<T *>(a.ell_out), n_ell, static_cast<T *>(a.q_out), n_q, ell0);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_copy_state(const StepArgs &a, int nd, int storage, hipStream_t s) {
+    const size_t n_ell = (size_t)a.B * a.nl * a.V;
+    const size_t n_q = (size_t)a.B * a.nn * nd * a.V;
+    return dispatch_type(storage, [&]<typename T>() {
+        k_copy<T><<<stride_blocks(n_q), kBlock, 0, s>>>(
+            static_cast<const T *>(a.ell_in), static_cast<T *>(a.ell_out), n_ell,
+            static_cast<const T *>(a.q_in), static_cast<T *>(a.q_out), n_q);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_upload(const ConstBlock &c, float *dst, hipStream_t s) {
+    k_upload<<<(kConstFloats + kBlock - 1) / kBlock, kBlock, 0, s>>>(c, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_label(const StepArgs &a, bool ident, int nd, int storage, hipStream_t s) {
+    return dispatch(nd, storage, ident, a.nl, a.nn,
+                    [&]<int ND, int NL, int NN, bool ID, typename T>() {
+                        k_label<ND, NL, NN, ID, T><<<voxel_grid(a), kBlock, 0, s>>>(a);
+                        return hipGetLastError();
+                    });
+}
+
+hipError_t launch_flow(const StepArgs &a, bool ident, int nd, int storage, hipStream_t s) {
+    return dispatch(nd, storage, ident, a.nl, a.nn,
+                    [&]<int ND, int NL, int NN, bool ID, typename T>() {
+                        k_flow<ND, NL, NN, ID, T><<<voxel_grid(a), kBlock, 0, s>>>(a);
+                        return hipGetLastError();
+                    });
+}
+
+bool fused_supported(int, int, int, bool) { return false; }
+
+hipError_t launch_fused(const StepArgs &, bool, int, int, hipStream_t) {
+    return hipErrorNotSupported;
+}
+
+hipError_t launch_energy(const StepArgs &a, bool ident, int nd, int storage,
+                         double *partials, double *results, hipStream_t s) {
+    hipError_t e = dispatch(nd, storage, ident, a.nl, a.nn,
+                            [&]<int ND, int NL, int NN, bool ID, typename T>() {
+                                k_energy<ND, NL, NN, ID, T>
+                                    <<<kPartials, kBlock, 0, s>>>(a, partials);
+                                return hipGetLastError();
+                            });
+    if (e != hipSuccess) return e;
+    k_reduce<<<1, kBlock, 0, s>>>(partials, kPartials, results);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(const StepArgs &a, int nd, int storage, float *u, int32_t *labels,
+                         float *q, hipStream_t s) {
+    return dispatch_type(storage, [&]<typename T>() {
+        if (nd == 2)
+            k_export<2, T><<<voxel_grid(a), kBlock, 0, s>>>(a, u, labels, q);
+        else
+            k_export<3, T><<<voxel_grid(a), kBlock, 0, s>>>(a, u, labels, q);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_check(const StepArgs &a, int32_t *flag, hipStream_t s) {
+    k_zero_flag<<<1, 64, 0, s>>>(flag);
+    const size_t nD = (size_t)a.B * a.nl * a.V;
+    size_t nS = 0;
+    if (a.s_mode == PF_S_SHARED_FIELD) nS = (size_t)a.B * a.V;
+    if (a.s_mode == PF_S_NODE_FIELD) nS = (size_t)a.B * a.nn * a.V;
+    k_check<<<stride_blocks(nD), kBlock, 0, s>>>(a.D, nD, a.S, nS, flag);
+    return hipGetLastError();
+}
+
+}  // namespace pf

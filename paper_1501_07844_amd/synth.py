@@ -30,6 +30,7 @@ __all__ = [
     "LabelGraph", "Problem", "potts_graph", "potts2d_rects", "potts3d_voronoi",
     "hmf_ellipsoids", "dagmf_blobs", "diff_batch", "random_potts",
     "random_tree", "random_dag", "random_problem", "CONFIGS", "make_config",
+    "ishikawa_levels", "hmf_tree", "dagmf_graph",
 ]
 
 
@@ -88,6 +89,8 @@ class Problem:
 
     @property
     def n_node(self) -> int:
+        if self.kind == "ishikawa":
+            return self.n_leaf - 1
         return self.graph.n_node
 
     @property
@@ -280,6 +283,35 @@ def diff_batch(seed: int = 5, batch: int = 16, ny: int = 256, nx: int = 256,
     return Problem("diff_batch", 2, D, S, "shared_field", potts_graph(5),
                    g.astype(np.int32), c=2.0, tau=0.125, iters=iters,
                    extra={"checkpoint_every": 10})
+
+
+def ishikawa_levels(seed: int = 6, shape: Tuple[int, int, int] = (1, 96, 128),
+                    n_levels: int = 4, iters: int = 200) -> Problem:
+    """Ordered-label workload for the Ishikawa chain: a smooth random field
+    (sum of 12 Gaussian bumps) quantised into n_levels + 1 ordered levels,
+    level means i / n_levels, noise 0.1, Gaussian-NLL data terms and one
+    constant S per flow drawn from U[0.2, 0.6].  2-D when Z == 1."""
+    rng = np.random.default_rng(seed)
+    Z, Y, X = shape
+    ext = np.array([Z, Y, X], np.float64)
+    zz = np.arange(Z, dtype=np.float64)[:, None, None]
+    yy = np.arange(Y, dtype=np.float64)[None, :, None]
+    xx = np.arange(X, dtype=np.float64)[None, None, :]
+    f = np.zeros(shape)
+    for _ in range(12):
+        c = rng.uniform(0.0, 1.0, size=3) * ext
+        r = rng.uniform(0.1, 0.3) * float(np.max(ext))
+        f += rng.uniform(-1.0, 1.0) * np.exp(-((zz - c[0]) ** 2 + (yy - c[1]) ** 2
+                                               + (xx - c[2]) ** 2) / (2 * r * r))
+    f = (f - f.min()) / max(f.max() - f.min(), 1e-12)
+    g = np.minimum((f * (n_levels + 1)).astype(np.int32), n_levels)
+    mu = np.arange(n_levels + 1) / n_levels
+    I = mu[g] + 0.1 * rng.standard_normal(shape)
+    D = _gaussian_nll(I, mu, 0.1)[None]
+    S = rng.uniform(0.2, 0.6, size=n_levels).astype(np.float32)
+    return Problem("ishikawa_levels", 2 if Z == 1 else 3, D, S, "node_scalar",
+                   potts_graph(n_levels + 1), g[None].astype(np.int32), c=2.0, tau=0.0625,
+                   iters=iters, kind="ishikawa")
 
 
 # ------------------------------------------------------ generic fixtures ---
