@@ -113,7 +113,7 @@ def main() -> int:
     fused = args.kernel == "fused" or (args.kernel == "auto" and res.workspace.numel() >
                                        pf.workspace_bytes(p.shape, p.n_leaf, n_node, 3, "fp32",
                                                           "two_pass"))
-    kernel_name = "k_fused_potts" if fused else "k_label+k_flow"
+    kernel_name = "k_fused" if fused else "k_label+k_flow"
     bytes_alg = (2 * 4 * (p.n_leaf + 3 * n_node) + 4 * p.n_leaf + 4) * V   # per iteration
     avg_ms = kms / max(kn, 1)
     achieved = bytes_alg / (avg_ms * 1e-3) / 1e9

@@ -276,8 +276,17 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
     a.s_mode = p.s_mode;
     a.D = p.D;
     a.S = p.S;
-    a.s_node = consts;
     a.W = consts + PF_MAX_NODES;
+    if (p.s_mode == PF_S_NODE_SCALAR) {
+        a.Sp = consts;
+        a.s_sb = 0, a.s_sa = 1, a.s_sv = 0;
+    } else if (p.s_mode == PF_S_SHARED_FIELD) {
+        a.Sp = p.S;
+        a.s_sb = a.V, a.s_sa = 0, a.s_sv = 1;
+    } else {
+        a.Sp = p.S;
+        a.s_sb = (int64_t)p.nn * a.V, a.s_sa = a.V, a.s_sv = 1;
+    }
     a.ell_in = a.ell_out = ell[0];
     a.q_in = a.q_out = q[0];
 

@@ -1,0 +1,214 @@
+// Device helpers shared by the iteration kernels (pf_kernels.hip and
+// pf_fused.hip), so that the two-pass and the fused single-pass kernels
+// evaluate the same float32 expressions in the same order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "pf_internal.h"
+
+namespace pf {
+namespace dev {
+
+// ------------------------------------------------------------ storage ----
+
+struct bf16s {
+    uint16_t b;
+};
+using f16s = _Float16;
+
+__device__ __forceinline__ float ld(const float *p, size_t i) { return p[i]; }
+__device__ __forceinline__ float ld(const bf16s *p, size_t i) {
+    return __uint_as_float(uint32_t(p[i].b) << 16);
+}
+__device__ __forceinline__ float ld(const f16s *p, size_t i) { return (float)p[i]; }
+
+__device__ __forceinline__ void st(float *p, size_t i, float v) { p[i] = v; }
+__device__ __forceinline__ void st(bf16s *p, size_t i, float v) {
+    // round to nearest even; NaN stays a quiet NaN
+    uint32_t u = __float_as_uint(v);
+    uint16_t r;
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+        r = uint16_t((u >> 16) | 0x40u);
+    } else {
+        u += 0x7fffu + ((u >> 16) & 1u);
+        r = uint16_t(u >> 16);
+    }
+    p[i].b = r;
+}
+__device__ __forceinline__ void st(f16s *p, size_t i, float v) { p[i] = (f16s)v; }
+
+// Per-solve constants (node capacities, path weights) live in the workspace
+// and are read through the constant address space: uniform across the
+// wavefront and never written by the iteration kernels, so they become
+// scalar loads.
+using cfloat = const __attribute__((address_space(4))) float;
+__device__ __forceinline__ float cld(const float *p, int i) {
+    return ((cfloat *)p)[i];
+}
+__device__ __forceinline__ float wgt(const StepArgs &a, int A, int L) {
+    return cld(a.W, A * PF_MAX_LEAVES + L);
+}
+
+// ------------------------------------------------------------ helpers ----
+
+struct Coord {
+    int x, y, z;
+};
+
+__device__ __forceinline__ Coord coord_of(int v, int nx, int ny) {
+    Coord c;
+    c.x = v % nx;
+    const int r = v / nx;
+    c.y = r % ny;
+    c.z = r / ny;
+    return c;
+}
+
+// S_A at voxel v of problem b, one strided load for every s_mode.  (A
+// three-way branch on s_mode here was miscompiled by hipcc 7.2 in the fully
+// unrolled weighted fp64 reduction: on the per-node-field path the node index
+// feeding the following flow address was read from a register that path never
+// wrote.  The branch-free form leaves no such path.)
+__device__ __forceinline__ float smooth(const StepArgs &a, int b, int A, int v) {
+    return a.Sp[(int64_t)b * a.s_sb + (int64_t)A * a.s_sa + (int64_t)v * a.s_sv];
+}
+
+// div q_A at (c, v): sum_k q_k(x)[x_k < N_k - 1] - q_k(x - e_k)[x_k > 0].
+template <int ND, typename T>
+__device__ __forceinline__ float divergence(const T *qa, size_t V, int v, const Coord &c,
+                                            const StepArgs &a) {
+    float dv = 0.f;
+    if (c.x < a.nx - 1) dv += ld(qa, v);
+    if (c.x > 0) dv -= ld(qa, v - 1);
+    const T *qy = qa + V;
+    if (c.y < a.ny - 1) dv += ld(qy, v);
+    if (c.y > 0) dv -= ld(qy, v - a.nx);
+    if constexpr (ND == 3) {
+        const T *qz = qa + 2 * V;
+        const int sz = a.nx * a.ny;
+        if (c.z < a.nz - 1) dv += ld(qz, v);
+        if (c.z > 0) dv -= ld(qz, v - sz);
+    }
+    return dv;
+}
+
+// Value after a round trip through the storage type (what a later load of a
+// stored value returns).
+__device__ __forceinline__ float roundtrip(float v, const float *) { return v; }
+__device__ __forceinline__ float roundtrip(float v, const bf16s *) {
+    bf16s t;
+    st(&t, 0, v);
+    return ld(&t, 0);
+}
+__device__ __forceinline__ float roundtrip(float v, const f16s *) { return (float)(f16s)v; }
+
+// Projected gradient step of one flow at one voxel:
+// p = q - c tau G (component k forced to 0 where x_k is the last index),
+// then p * min(1, S / |p|).
+template <int ND>
+__device__ __forceinline__ void flow_project(const StepArgs &a, const float (&q)[ND],
+                                             const float (&G)[3], const bool (&h)[3], float S,
+                                             float (&p)[ND]) {
+#pragma unroll
+    for (int k = 0; k < ND; ++k) p[k] = h[k] ? fmaf(-a.ctau, G[k], q[k]) : 0.f;
+    float n2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) n2 = fmaf(p[k], p[k], n2);
+    if (n2 > S * S) {
+        const float sc = S * rsqrtf(n2);
+#pragma unroll
+        for (int k = 0; k < ND; ++k) p[k] *= sc;
+    }
+}
+
+// Gradient step and projection of flow A at voxel v given grad U_A, reading
+// and writing the flow in memory.
+template <int ND, typename T>
+__device__ __forceinline__ void flow_update(const StepArgs &a, int b, int A, int v,
+                                            const float (&G)[3], const bool (&h)[3]) {
+    const size_t V = (size_t)a.V;
+    const size_t base = ((size_t)b * a.nn + A) * ND * V + v;
+    const T *qa = static_cast<const T *>(a.q_in) + base;
+    T *qo = static_cast<T *>(a.q_out) + base;
+    float q[ND], p[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) q[k] = ld(qa, k * V);
+    flow_project<ND>(a, q, G, h, smooth(a, b, A, v), p);
+#pragma unroll
+    for (int k = 0; k < ND; ++k) st(qo, k * V, p[k]);
+}
+
+// Top-down flow excess in path-weight form: d_L += W[A][L] * div q_A
+// (identity for Potts).
+template <int NLMAX, bool IDENT>
+__device__ __forceinline__ void add_excess(const StepArgs &a, float (&d)[NLMAX], int A, float dv) {
+    if constexpr (IDENT) {
+        d[A] += dv;
+    } else {
+#pragma unroll
+        for (int L = 0; L < NLMAX; ++L) {
+            if (L < a.nl) {
+                const float w = wgt(a, A, L);
+                if (w != 0.f) d[L] = fmaf(w, dv, d[L]);
+            }
+        }
+    }
+}
+
+// Entropic proximal (Bregman) label step in the log domain:
+// ell_L <- (t_L - m) - ln sum_L' exp(t_L' - m),  t_L = ell_L - d_L / c,  m = max t.
+template <int NLMAX>
+__device__ __forceinline__ void entropic_step(const StepArgs &a, const float (&d)[NLMAX],
+                                              float (&ell)[NLMAX]) {
+    float m = -INFINITY;
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L) {
+        if (L < a.nl) {
+            ell[L] = fmaf(-d[L], a.inv_c, ell[L]);
+            m = fmaxf(m, ell[L]);
+        }
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L)
+        if (L < a.nl) s += __expf(ell[L] - m);
+    const float ls = __logf(s);
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L)
+        if (L < a.nl) ell[L] = (ell[L] - m) - ls;
+}
+
+// grad U_A for every flow A from the leaf gradients gu (path-weight form)
+// and the projected gradient step of each flow at voxel v.
+template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
+__device__ __forceinline__ void flows_from_leaf_gradients(const StepArgs &a, int b, int v,
+                                                          const float (&gu)[NLMAX][ND],
+                                                          const bool (&h)[3]) {
+#pragma unroll
+    for (int A = 0; A < NNMAX; ++A) {
+        if (A < a.nn) {
+            float G[3] = {0.f, 0.f, 0.f};
+            if constexpr (IDENT) {
+#pragma unroll
+                for (int k = 0; k < ND; ++k) G[k] = gu[A][k];
+            } else {
+#pragma unroll
+                for (int L = 0; L < NLMAX; ++L) {
+                    if (L < a.nl) {
+                        const float w = wgt(a, A, L);
+                        if (w != 0.f) {
+#pragma unroll
+                            for (int k = 0; k < ND; ++k) G[k] = fmaf(w, gu[L][k], G[k]);
+                        }
+                    }
+                }
+            }
+            flow_update<ND, T>(a, b, A, v, G, h);
+        }
+    }
+}
+
+}  // namespace dev
+}  // namespace pf

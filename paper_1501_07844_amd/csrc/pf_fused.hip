@@ -1,0 +1,299 @@
+// Fused single-pass iteration for gfx950: one kernel per iteration reads the
+// label and flow state once and writes the next state once (ping-pong
+// buffers), instead of the label pass + flow pass that read the flows and
+// labels twice.
+//
+// Dependencies of one iteration at voxel x (Algorithms 1 and 2):
+//   label step at x needs the old flows at x and x - e_k (divergence);
+//   flow step at x needs the NEW labels at x and x + e_k (forward gradient).
+// A block therefore owns a FTX x FTY tile of (x, y) columns and marches a
+// chunk of z planes.  Along z the forward neighbour is the thread's own next
+// plane (kept in registers, together with the old q_z of the previous plane
+// for the divergence).  Along x and y the new labels of the plane are
+// exchanged through LDS; the labels one column past the tile (x) and one row
+// past it (y) belong to the neighbouring tiles and are recomputed here by one
+// extra "halo" wavefront.  Each point's label step, flow step and rounding
+// are the expressions of the two-pass kernels, so both variants give the same
+// state bit for bit.
+//
+// Block -> tile mapping is XCD-aware: consecutive hardware block ids land on
+// different XCDs, so they are remapped to give each XCD a contiguous range
+// of tiles (neighbouring tiles then share that XCD's L2 for the halo reads).
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "pf_device.h"
+#include "pf_internal.h"
+
+namespace pf {
+namespace {
+
+using namespace dev;
+
+constexpr int FTX = 64;               // tile width = one wavefront
+constexpr int FTY = 8;                // owned rows per tile
+constexpr int FTHREADS = FTX * (FTY + 1);
+
+// Label step at voxel (x, y, z) of problem b.  qzb holds the old q_z of every
+// flow one plane below (ignored at z == 0).  Returns the new labels as the
+// exponential of the stored-precision log-label (what the two-pass flow
+// kernel reads back), the old flows at the voxel in qpt, and stores the new
+// log-labels when `store`.
+template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
+__device__ __forceinline__ void label_point(const StepArgs &a, int b, int x, int y, int z,
+                                            const float (&qzb)[NNMAX], bool store,
+                                            float (&u)[NLMAX], float (&qpt)[NNMAX][ND]) {
+    const size_t V = (size_t)a.V;
+    const int v = (z * a.ny + y) * a.nx + x;
+    const T *q = static_cast<const T *>(a.q_in);
+    const T *ell = static_cast<const T *>(a.ell_in);
+    float d[NLMAX], e[NLMAX];
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L)
+        if (L < a.nl) d[L] = a.D[((size_t)b * a.nl + L) * V + v];
+#pragma unroll
+    for (int A = 0; A < NNMAX; ++A) {
+        if (A < a.nn) {
+            const T *qa = q + ((size_t)b * a.nn + A) * ND * V;
+#pragma unroll
+            for (int k = 0; k < ND; ++k) qpt[A][k] = ld(qa, k * V + v);
+            // same order of operations as dev::divergence
+            float dv = 0.f;
+            if (x < a.nx - 1) dv += qpt[A][0];
+            if (x > 0) dv -= ld(qa, v - 1);
+            if (y < a.ny - 1) dv += qpt[A][1];
+            if (y > 0) dv -= ld(qa + V, v - a.nx);
+            if constexpr (ND == 3) {
+                if (z < a.nz - 1) dv += qpt[A][2];
+                if (z > 0) dv -= qzb[A];
+            }
+            add_excess<NLMAX, IDENT>(a, d, A, dv);
+        }
+    }
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L)
+        if (L < a.nl) e[L] = ld(ell, ((size_t)b * a.nl + L) * V + v);
+    entropic_step<NLMAX>(a, d, e);
+    T *out = static_cast<T *>(a.ell_out);
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L) {
+        if (L < a.nl) {
+            if (store) st(out, ((size_t)b * a.nl + L) * V + v, e[L]);
+            u[L] = __expf(roundtrip(e[L], static_cast<const T *>(nullptr)));
+        }
+    }
+}
+
+template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
+__global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
+    __shared__ float lds[NLMAX][FTY + 1][FTX + 1];
+    const int wave = threadIdx.x / FTX;
+    const int lane = threadIdx.x % FTX;
+
+    // XCD-aware block -> tile mapping
+    const int nb = gridDim.x;
+    const int pb = blockIdx.x;
+    const int lb = (nb % 8 == 0) ? (pb % 8) * (nb / 8) + pb / 8 : pb;
+    const int bx = lb % g.tiles_x;
+    int r = lb / g.tiles_x;
+    const int by = r % g.tiles_y;
+    r /= g.tiles_y;
+    const int ch = r % g.n_chunks;
+    const int b = r / g.n_chunks;
+    const int x0 = bx * FTX, y0 = by * FTY;
+    const int zs = ch * g.cz;
+    const int ze = min(a.nz, zs + g.cz);
+
+    const bool halo = wave == FTY;
+    // point A: owned voxel column, or the halo row past the tile
+    const int xa = x0 + lane, ya = y0 + wave;
+    const bool va = xa < a.nx && ya < a.ny;
+    const bool own = !halo && va;
+    // point B (halo wavefront only): the column past the tile
+    const int xb = x0 + FTX, yb = y0 + lane;
+    const bool vb = halo && lane < FTY && xb < a.nx && yb < a.ny;
+
+    const size_t V = (size_t)a.V;
+    const T *q = static_cast<const T *>(a.q_in);
+    T *qout = static_cast<T *>(a.q_out);
+
+    float ua[NLMAX], ub[NLMAX];
+    float qa[NNMAX][ND], qb[NNMAX][ND];
+    float qzb[NNMAX];
+
+    // prologue: labels of plane zs (point A and B), old q_z of plane zs - 1
+    if (va) {
+        if (ND == 3 && zs > 0) {
+            const int vbelow = ((zs - 1) * a.ny + ya) * a.nx + xa;
+#pragma unroll
+            for (int A = 0; A < NNMAX; ++A)
+                if (A < a.nn) qzb[A] = ld(q, (((size_t)b * a.nn + A) * ND + 2) * V + vbelow);
+        }
+        label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xa, ya, zs, qzb, own, ua, qa);
+#pragma unroll
+        for (int L = 0; L < NLMAX; ++L)
+            if (L < a.nl) lds[L][wave][lane] = ua[L];
+    }
+    if (vb) {
+        if (ND == 3 && zs > 0) {
+            const int vbelow = ((zs - 1) * a.ny + yb) * a.nx + xb;
+#pragma unroll
+            for (int A = 0; A < NNMAX; ++A)
+                if (A < a.nn) qzb[A] = ld(q, (((size_t)b * a.nn + A) * ND + 2) * V + vbelow);
+        }
+        label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xb, yb, zs, qzb, false, ub, qb);
+#pragma unroll
+        for (int L = 0; L < NLMAX; ++L)
+            if (L < a.nl) lds[L][lane][FTX] = ub[L];
+    }
+    __syncthreads();
+
+    for (int z = zs; z < ze; ++z) {
+        const bool has_next = z + 1 < a.nz;
+        float un[NLMAX], qn[NNMAX][ND];
+        // labels of plane z + 1 (owned when z + 1 < ze, else the halo plane)
+        if (va && has_next) {
+            float qz[NNMAX];
+#pragma unroll
+            for (int A = 0; A < NNMAX; ++A)
+                if (A < a.nn) qz[A] = qa[A][ND - 1];
+            label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xa, ya, z + 1, qz, own && z + 1 < ze,
+                                                    un, qn);
+        }
+        float ubn[NLMAX];
+        if (vb && has_next) {
+            float qz[NNMAX];
+#pragma unroll
+            for (int A = 0; A < NNMAX; ++A)
+                if (A < a.nn) qz[A] = qb[A][ND - 1];
+            label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xb, yb, z + 1, qz, false, ubn, qb);
+        }
+        // flow step of the owned voxels of plane z
+        if (own) {
+            const int v = (z * a.ny + ya) * a.nx + xa;
+            const bool h[3] = {xa < a.nx - 1, ya < a.ny - 1, ND == 3 && has_next};
+            float gu[NLMAX][ND];
+#pragma unroll
+            for (int L = 0; L < NLMAX; ++L) {
+                if (L < a.nl) {
+                    gu[L][0] = h[0] ? lds[L][wave][lane + 1] - ua[L] : 0.f;
+                    gu[L][1] = h[1] ? lds[L][wave + 1][lane] - ua[L] : 0.f;
+                    if constexpr (ND == 3) gu[L][2] = h[2] ? un[L] - ua[L] : 0.f;
+                }
+            }
+#pragma unroll
+            for (int A = 0; A < NNMAX; ++A) {
+                if (A < a.nn) {
+                    float G[3] = {0.f, 0.f, 0.f};
+                    if constexpr (IDENT) {
+#pragma unroll
+                        for (int k = 0; k < ND; ++k) G[k] = gu[A][k];
+                    } else {
+#pragma unroll
+                        for (int L = 0; L < NLMAX; ++L) {
+                            if (L < a.nl) {
+                                const float w = wgt(a, A, L);
+                                if (w != 0.f) {
+#pragma unroll
+                                    for (int k = 0; k < ND; ++k) G[k] = fmaf(w, gu[L][k], G[k]);
+                                }
+                            }
+                        }
+                    }
+                    float p[ND];
+                    flow_project<ND>(a, qa[A], G, h, smooth(a, b, A, v), p);
+                    T *qo = qout + ((size_t)b * a.nn + A) * ND * V + v;
+#pragma unroll
+                    for (int k = 0; k < ND; ++k) st(qo, k * V, p[k]);
+                }
+            }
+        }
+        __syncthreads();   // plane z of the LDS is no longer read
+        if (has_next) {
+            if (va) {
+#pragma unroll
+                for (int L = 0; L < NLMAX; ++L) {
+                    if (L < a.nl) {
+                        lds[L][wave][lane] = un[L];
+                        ua[L] = un[L];
+                    }
+                }
+#pragma unroll
+                for (int A = 0; A < NNMAX; ++A)
+#pragma unroll
+                    for (int k = 0; k < ND; ++k)
+                        if (A < a.nn) qa[A][k] = qn[A][k];
+            }
+            if (vb) {
+#pragma unroll
+                for (int L = 0; L < NLMAX; ++L)
+                    if (L < a.nl) lds[L][lane][FTX] = ubn[L];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int ND, typename T, typename F>
+hipError_t fused_bucket(bool ident, int nl, int nn, F &f) {
+    if (ident) {
+        if (nl <= 4) return f.template operator()<ND, 4, 4, true, T>();
+        if (nl <= 8) return f.template operator()<ND, 8, 8, true, T>();
+        return f.template operator()<ND, 16, 16, true, T>();
+    }
+    if (nl <= 4 && nn <= 8) return f.template operator()<ND, 4, 8, false, T>();
+    if (nl <= 8 && nn <= 16) return f.template operator()<ND, 8, 16, false, T>();
+    return f.template operator()<ND, 16, 16, false, T>();
+}
+
+template <typename F>
+hipError_t fused_dispatch(int nd, int storage, bool ident, int nl, int nn, F &&f) {
+    if (nd == 2) {
+        if (storage == PF_BF16) return fused_bucket<2, bf16s>(ident, nl, nn, f);
+        if (storage == PF_FP16) return fused_bucket<2, f16s>(ident, nl, nn, f);
+        return fused_bucket<2, float>(ident, nl, nn, f);
+    }
+    if (storage == PF_BF16) return fused_bucket<3, bf16s>(ident, nl, nn, f);
+    if (storage == PF_FP16) return fused_bucket<3, f16s>(ident, nl, nn, f);
+    return fused_bucket<3, float>(ident, nl, nn, f);
+}
+
+}  // namespace
+
+bool fused_supported(int nd, int nl, int nn, bool identity) {
+    (void)nd;
+    if (identity) return nl <= 16;
+    return nl <= 16 && nn <= 16;
+}
+
+FusedGeom fused_geometry(const StepArgs &a) {
+    FusedGeom g{};
+    g.tiles_x = (a.nx + FTX - 1) / FTX;
+    g.tiles_y = (a.ny + FTY - 1) / FTY;
+    const long tiles = (long)g.tiles_x * g.tiles_y * a.B;
+    // aim for about two resident blocks per compute unit on 256 CUs, with
+    // chunks of at least 16 planes (each chunk recomputes one extra plane)
+    const long target = 512;
+    long chunks = (target + tiles - 1) / tiles;
+    const long max_chunks = (a.nz + 15) / 16;
+    if (chunks > max_chunks) chunks = max_chunks;
+    if (chunks < 1) chunks = 1;
+    g.cz = (int)((a.nz + chunks - 1) / chunks);
+    g.n_chunks = (a.nz + g.cz - 1) / g.cz;
+    g.blocks = tiles * g.n_chunks;
+    return g;
+}
+
+hipError_t launch_fused(const StepArgs &a, bool ident, int nd, int storage, hipStream_t s) {
+    const FusedGeom g = fused_geometry(a);
+    if (g.blocks <= 0 || g.blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    return fused_dispatch(nd, storage, ident, a.nl, a.nn,
+                          [&]<int ND, int NL, int NN, bool ID, typename T>() {
+                              k_fused<ND, NL, NN, ID, T>
+                                  <<<(unsigned)g.blocks, FTHREADS, 0, s>>>(a, g);
+                              return hipGetLastError();
+                          });
+}
+
+}  // namespace pf

@@ -36,10 +36,15 @@ struct StepArgs {
     int32_t nl, nn;          // end-labels, flows
     float inv_c;             // 1/c
     float ctau;              // c * tau
-    int32_t s_mode;          // pf_s_mode
+    int32_t s_mode;          // pf_s_mode (input check only)
     const float *D;          // [B][nl][V]
-    const float *S;          // field (shared or per node) or null
-    const float *s_node;     // workspace copy of ConstBlock::s_node
+    const float *S;          // user field (shared or per node) or null
+    // Capacity S_A at voxel v of problem b is Sp[b*s_sb + A*s_sa + v*s_sv]
+    // for every s_mode (a single branch-free form): node constants come from
+    // the workspace copy with strides (0, 1, 0), a shared field has
+    // (V, 0, 1) and a per-node field (nn*V, V, 1).
+    const float *Sp;
+    int64_t s_sb, s_sa, s_sv;
     const float *W;          // workspace copy of ConstBlock::w, [A * PF_MAX_LEAVES + L]
     const void *ell_in;      // storage [B][nl][V]
     const void *q_in;        // storage [B][nn][nd][V]
@@ -58,6 +63,12 @@ struct Layout {
     size_t total;
 };
 
+// Launch geometry of the fused kernel: (x, y) tiles times z chunks times problems.
+struct FusedGeom {
+    int32_t tiles_x, tiles_y, n_chunks, cz;
+    long blocks;
+};
+
 constexpr int kPartials = 1024;
 constexpr int kBlock = 256;
 
@@ -71,6 +82,7 @@ hipError_t launch_label(const StepArgs &a, bool ident, int nd, int storage, hipS
 hipError_t launch_flow(const StepArgs &a, bool ident, int nd, int storage, hipStream_t s);
 hipError_t launch_fused(const StepArgs &a, bool ident, int nd, int storage, hipStream_t s);
 bool fused_supported(int nd, int nl, int nn, bool identity);
+FusedGeom fused_geometry(const StepArgs &a);
 hipError_t launch_copy_state(const StepArgs &a, int nd, int storage, hipStream_t s);
 hipError_t launch_energy(const StepArgs &a, bool ident, int nd, int storage,
                          double *partials, double *results, hipStream_t s);

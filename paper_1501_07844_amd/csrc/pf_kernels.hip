@@ -17,91 +17,13 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "pf_device.h"
 #include "pf_internal.h"
 
 namespace pf {
 namespace {
 
-// ------------------------------------------------------------ storage ----
-
-struct bf16s {
-    uint16_t b;
-};
-using f16s = _Float16;
-
-__device__ __forceinline__ float ld(const float *p, size_t i) { return p[i]; }
-__device__ __forceinline__ float ld(const bf16s *p, size_t i) {
-    return __uint_as_float(uint32_t(p[i].b) << 16);
-}
-__device__ __forceinline__ float ld(const f16s *p, size_t i) { return (float)p[i]; }
-
-__device__ __forceinline__ void st(float *p, size_t i, float v) { p[i] = v; }
-__device__ __forceinline__ void st(bf16s *p, size_t i, float v) {
-    // round to nearest even; NaN stays a quiet NaN
-    uint32_t u = __float_as_uint(v);
-    uint16_t r;
-    if ((u & 0x7fffffffu) > 0x7f800000u) {
-        r = uint16_t((u >> 16) | 0x40u);
-    } else {
-        u += 0x7fffu + ((u >> 16) & 1u);
-        r = uint16_t(u >> 16);
-    }
-    p[i].b = r;
-}
-__device__ __forceinline__ void st(f16s *p, size_t i, float v) { p[i] = (f16s)v; }
-
-// Per-solve constants (node capacities, path weights) live in the workspace
-// and are read through the constant address space: uniform across the
-// wavefront and never written by the iteration kernels, so they become
-// scalar loads.
-using cfloat = const __attribute__((address_space(4))) float;
-__device__ __forceinline__ float cld(const float *p, int i) {
-    return ((cfloat *)p)[i];
-}
-__device__ __forceinline__ float wgt(const StepArgs &a, int A, int L) {
-    return cld(a.W, A * PF_MAX_LEAVES + L);
-}
-
-// ------------------------------------------------------------ helpers ----
-
-struct Coord {
-    int x, y, z;
-};
-
-__device__ __forceinline__ Coord coord_of(int v, int nx, int ny) {
-    Coord c;
-    c.x = v % nx;
-    const int r = v / nx;
-    c.y = r % ny;
-    c.z = r / ny;
-    return c;
-}
-
-// S_A at voxel v of problem b.
-__device__ __forceinline__ float smooth(const StepArgs &a, int b, int A, int v) {
-    if (a.s_mode == PF_S_NODE_SCALAR) return cld(a.s_node, A);
-    if (a.s_mode == PF_S_SHARED_FIELD) return a.S[(size_t)b * a.V + v];
-    return a.S[((size_t)b * a.nn + A) * a.V + v];
-}
-
-// div q_A at (c, v): sum_k q_k(x)[x_k < N_k - 1] - q_k(x - e_k)[x_k > 0].
-template <int ND, typename T>
-__device__ __forceinline__ float divergence(const T *qa, size_t V, int v, const Coord &c,
-                                            const StepArgs &a) {
-    float dv = 0.f;
-    if (c.x < a.nx - 1) dv += ld(qa, v);
-    if (c.x > 0) dv -= ld(qa, v - 1);
-    const T *qy = qa + V;
-    if (c.y < a.ny - 1) dv += ld(qy, v);
-    if (c.y > 0) dv -= ld(qy, v - a.nx);
-    if constexpr (ND == 3) {
-        const T *qz = qa + 2 * V;
-        const int sz = a.nx * a.ny;
-        if (c.z < a.nz - 1) dv += ld(qz, v);
-        if (c.z > 0) dv -= ld(qz, v - sz);
-    }
-    return dv;
-}
+using namespace dev;
 
 // --------------------------------------------------------- label pass ----
 
@@ -116,7 +38,7 @@ __device__ __forceinline__ void label_body(const StepArgs &a) {
     const T *ell = static_cast<const T *>(a.ell_in);
     T *out = static_cast<T *>(a.ell_out);
 
-    float d[NLMAX];
+    float d[NLMAX], e[NLMAX];
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L)
         if (L < a.nl) d[L] = a.D[((size_t)b * a.nl + L) * V + v];
@@ -124,38 +46,16 @@ __device__ __forceinline__ void label_body(const StepArgs &a) {
     for (int A = 0; A < NNMAX; ++A) {
         if (A < a.nn) {
             const T *qa = q + ((size_t)b * a.nn + A) * ND * V;
-            const float dv = divergence<ND>(qa, V, v, c, a);
-            if constexpr (IDENT) {
-                d[A] += dv;
-            } else {
-#pragma unroll
-                for (int L = 0; L < NLMAX; ++L) {
-                    if (L < a.nl) {
-                        const float w = wgt(a, A, L);
-                        if (w != 0.f) d[L] = fmaf(w, dv, d[L]);
-                    }
-                }
-            }
+            add_excess<NLMAX, IDENT>(a, d, A, divergence<ND>(qa, V, v, c, a));
         }
     }
-    // entropic proximal step, max-subtracted log-sum-exp in the log domain
-    float t[NLMAX];
-    float m = -INFINITY;
-#pragma unroll
-    for (int L = 0; L < NLMAX; ++L) {
-        if (L < a.nl) {
-            t[L] = fmaf(-d[L], a.inv_c, ld(ell, ((size_t)b * a.nl + L) * V + v));
-            m = fmaxf(m, t[L]);
-        }
-    }
-    float s = 0.f;
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L)
-        if (L < a.nl) s += __expf(t[L] - m);
-    const float ls = __logf(s);
+        if (L < a.nl) e[L] = ld(ell, ((size_t)b * a.nl + L) * V + v);
+    entropic_step<NLMAX>(a, d, e);
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L)
-        if (L < a.nl) st(out, ((size_t)b * a.nl + L) * V + v, (t[L] - m) - ls);
+        if (L < a.nl) st(out, ((size_t)b * a.nl + L) * V + v, e[L]);
 }
 
 template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
@@ -164,30 +64,6 @@ __global__ __launch_bounds__(kBlock) void k_label(StepArgs a) {
 }
 
 // ---------------------------------------------------------- flow pass ----
-
-// Gradient step and projection of flow A at voxel v given grad U_A.
-template <int ND, typename T>
-__device__ __forceinline__ void flow_update(const StepArgs &a, int b, int A, int v,
-                                            const float (&G)[3], const bool (&h)[3]) {
-    const size_t V = (size_t)a.V;
-    const size_t base = ((size_t)b * a.nn + A) * ND * V + v;
-    const T *qa = static_cast<const T *>(a.q_in) + base;
-    T *qo = static_cast<T *>(a.q_out) + base;
-    float p[ND];
-#pragma unroll
-    for (int k = 0; k < ND; ++k) p[k] = h[k] ? fmaf(-a.ctau, G[k], ld(qa, k * V)) : 0.f;
-    const float S = smooth(a, b, A, v);
-    float n2 = 0.f;
-#pragma unroll
-    for (int k = 0; k < ND; ++k) n2 = fmaf(p[k], p[k], n2);
-    if (n2 > S * S) {
-        const float sc = S * rsqrtf(n2);
-#pragma unroll
-        for (int k = 0; k < ND; ++k) p[k] *= sc;
-    }
-#pragma unroll
-    for (int k = 0; k < ND; ++k) st(qo, k * V, p[k]);
-}
 
 template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
 __device__ __forceinline__ void flow_body(const StepArgs &a) {
@@ -200,48 +76,17 @@ __device__ __forceinline__ void flow_body(const StepArgs &a) {
     const bool h[3] = {c.x < a.nx - 1, c.y < a.ny - 1, ND == 3 && c.z < a.nz - 1};
     const int off[3] = {1, a.nx, a.nx * a.ny};
 
-    if constexpr (IDENT) {
+    float gu[NLMAX][ND];
 #pragma unroll
-        for (int L = 0; L < NLMAX; ++L) {
-            if (L < a.nl) {
-                const T *e = ell + ((size_t)b * a.nl + L) * V + v;
-                const float u0 = __expf(ld(e, 0));
-                float G[3] = {0.f, 0.f, 0.f};
+    for (int L = 0; L < NLMAX; ++L) {
+        if (L < a.nl) {
+            const T *e = ell + ((size_t)b * a.nl + L) * V + v;
+            const float u0 = __expf(ld(e, 0));
 #pragma unroll
-                for (int k = 0; k < ND; ++k)
-                    if (h[k]) G[k] = __expf(ld(e, off[k])) - u0;
-                flow_update<ND, T>(a, b, L, v, G, h);
-            }
-        }
-    } else {
-        float gu[NLMAX][ND];
-#pragma unroll
-        for (int L = 0; L < NLMAX; ++L) {
-            if (L < a.nl) {
-                const T *e = ell + ((size_t)b * a.nl + L) * V + v;
-                const float u0 = __expf(ld(e, 0));
-#pragma unroll
-                for (int k = 0; k < ND; ++k) gu[L][k] = h[k] ? __expf(ld(e, off[k])) - u0 : 0.f;
-            }
-        }
-#pragma unroll
-        for (int A = 0; A < NNMAX; ++A) {
-            if (A < a.nn) {
-                float G[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-                for (int L = 0; L < NLMAX; ++L) {
-                    if (L < a.nl) {
-                        const float w = wgt(a, A, L);
-                        if (w != 0.f) {
-#pragma unroll
-                            for (int k = 0; k < ND; ++k) G[k] = fmaf(w, gu[L][k], G[k]);
-                        }
-                    }
-                }
-                flow_update<ND, T>(a, b, A, v, G, h);
-            }
+            for (int k = 0; k < ND; ++k) gu[L][k] = h[k] ? __expf(ld(e, off[k])) - u0 : 0.f;
         }
     }
+    flows_from_leaf_gradients<ND, NLMAX, NNMAX, IDENT, T>(a, b, v, gu, h);
 }
 
 template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
@@ -564,12 +409,6 @@ hipError_t launch_flow(const StepArgs &a, bool ident, int nd, int storage, hipSt
                         k_flow<ND, NL, NN, ID, T><<<voxel_grid(a), kBlock, 0, s>>>(a);
                         return hipGetLastError();
                     });
-}
-
-bool fused_supported(int, int, int, bool) { return false; }
-
-hipError_t launch_fused(const StepArgs &, bool, int, int, hipStream_t) {
-    return hipErrorNotSupported;
 }
 
 hipError_t launch_energy(const StepArgs &a, bool ident, int nd, int storage,

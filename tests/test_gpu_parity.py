@@ -198,3 +198,64 @@ def test_low_precision_storage_energy(name, kernel, storage):
           f"label mismatches {n_bad} ({n_dec} decisive) of {r.labels.numel()}", flush=True)
     assert rel <= 1e-3
     assert r.gap >= -1e-3 * abs(r.energy)
+
+
+@pytest.mark.parametrize("name", ["potts3d_voronoi_36x40x44", "hmf_ellipsoids_20x36x44",
+                                  "dagmf_blobs_18x30x38", "diff_batch_3x40x52"])
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+def test_fused_equals_two_pass_bitwise(name, storage):
+    """The fused single pass evaluates the two-pass expressions in the same
+    order, so the states agree bit for bit."""
+    p = WORKLOADS[name]()
+    a = gpu_solve(p, 40, kernel="two_pass", storage=storage, return_q=True)
+    b = gpu_solve(p, 40, kernel="fused", storage=storage, return_q=True)
+    assert torch.equal(a.u, b.u) and torch.equal(a.q, b.q) and torch.equal(a.labels, b.labels)
+    assert a.energy == b.energy and a.dual == b.dual
+
+
+def _patch_bounds(x, n, w=5):
+    lo = min(max(x - w // 2, 0), max(n - w, 0))
+    return lo, min(lo + w, n)
+
+
+@pytest.mark.parametrize("kernel", ["fused", "two_pass"])
+def test_full_size_sampled_one_step(kernel):
+    """At the full 256^3 Potts workload, in the launch configuration the
+    benchmark times: the state after k iterations, advanced by one more
+    iteration on the GPU, matches the float64 one-iteration map applied to 5^3
+    patches around sampled voxels (exact there: a patch edge that is not the
+    volume edge lies two voxels from the sample).  Also checks feasibility and
+    weak duality of the full-size state."""
+    p = synth.potts3d_voronoi(n=256, iters=20)
+    D, S = torch.from_numpy(p.D).cuda(), torch.from_numpy(p.S).cuda()
+    kw = dict(c=p.c, tau=p.tau, ndim=3, s_mode="shared_field", kernel=kernel, return_q=True)
+    r0 = pf.solve_potts(D, S, iters=20, final_energy=True, **kw)
+    assert r0.max_simplex_err < 1e-5 and r0.max_flow_excess <= 1e-6
+    assert r0.gap >= -1e-7 * abs(r0.energy)
+    u0, q0 = r0.u.clone(), r0.q.clone()
+    r1 = pf.solve_potts(D, S, iters=1, warm_start=True, workspace=r0.workspace,
+                        final_energy=False, **kw)
+    n = 256
+    rng = np.random.default_rng(99)
+    pts = [tuple(rng.integers(0, n, size=3)) for _ in range(40)]
+    pts += [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 17), (n - 1, 5, 0), (128, 0, n - 1)]
+    worst_u = worst_q = 0.0
+    for (z, y, x) in pts:
+        (z0, z1), (y0, y1), (x0, x1) = (_patch_bounds(z, n), _patch_bounds(y, n),
+                                        _patch_bounds(x, n))
+        sl = (slice(None), slice(None), slice(z0, z1), slice(y0, y1), slice(x0, x1))
+        u = u0[sl].double().cpu()
+        q = q0[:, :, :, z0:z1, y0:y1, x0:x1].double().cpu()
+        Dp = torch.tensor(p.D[sl], dtype=torch.float64)
+        Sp = torch.tensor(p.S[:, z0:z1, y0:y1, x0:x1], dtype=torch.float64).unsqueeze(1)
+        ell = torch.log(u)
+        ell1, q1, _ = O.potts_iteration(ell, q, Dp, Sp, p.c, p.tau, 3)
+        cz, cy, cx = z - z0, y - y0, x - x0
+        u_ref = torch.exp(ell1[0, :, cz, cy, cx])
+        u_gpu = r1.u[0, :, z, y, x].double().cpu()
+        q_ref = q1[0, :, :, cz, cy, cx]
+        q_gpu = r1.q[0, :, :, z, y, x].double().cpu()
+        worst_u = max(worst_u, float((u_ref - u_gpu).abs().max()))
+        worst_q = max(worst_q, float((q_ref - q_gpu).abs().max()))
+    print(f"[full-size one-step] {kernel}: max|du| {worst_u:.2e}, max|dq| {worst_q:.2e}", flush=True)
+    assert worst_u <= 1e-5 and worst_q <= 1e-5
