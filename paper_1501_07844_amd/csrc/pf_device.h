@@ -75,23 +75,30 @@ __device__ __forceinline__ float smooth(const StepArgs &a, int b, int A, int v) 
     return a.Sp[(int64_t)b * a.s_sb + (int64_t)A * a.s_sa + (int64_t)v * a.s_sv];
 }
 
-// div q_A at (c, v): sum_k q_k(x)[x_k < N_k - 1] - q_k(x - e_k)[x_k > 0].
-template <int ND, typename T>
-__device__ __forceinline__ float divergence(const T *qa, size_t V, int v, const Coord &c,
-                                            const StepArgs &a) {
+// div q_A from the flow components at x (q0) and at x - e_k (qm):
+// sum_k q_k(x)[x_k < N_k - 1] - q_k(x - e_k)[x_k > 0].  Selects, no branches.
+template <int ND>
+__device__ __forceinline__ float div_from(const float (&q0)[3], const float (&qm)[3],
+                                          const bool (&fwd)[3], const bool (&bwd)[3]) {
     float dv = 0.f;
-    if (c.x < a.nx - 1) dv += ld(qa, v);
-    if (c.x > 0) dv -= ld(qa, v - 1);
-    const T *qy = qa + V;
-    if (c.y < a.ny - 1) dv += ld(qy, v);
-    if (c.y > 0) dv -= ld(qy, v - a.nx);
-    if constexpr (ND == 3) {
-        const T *qz = qa + 2 * V;
-        const int sz = a.nx * a.ny;
-        if (c.z < a.nz - 1) dv += ld(qz, v);
-        if (c.z > 0) dv -= ld(qz, v - sz);
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+        dv += fwd[k] ? q0[k] : 0.f;
+        dv -= bwd[k] ? qm[k] : 0.f;
     }
     return dv;
+}
+
+// Offsets of the backward neighbours, 0 on the first index of an axis so
+// that the (unconditional) load stays inside the volume.
+__device__ __forceinline__ void backward_offsets(const Coord &c, const StepArgs &a, int (&m)[3],
+                                                 bool (&bwd)[3]) {
+    bwd[0] = c.x > 0;
+    bwd[1] = c.y > 0;
+    bwd[2] = c.z > 0;
+    m[0] = bwd[0] ? 1 : 0;
+    m[1] = bwd[1] ? a.nx : 0;
+    m[2] = bwd[2] ? a.nx * a.ny : 0;
 }
 
 // Value after a round trip through the storage type (what a later load of a
@@ -123,91 +130,55 @@ __device__ __forceinline__ void flow_project(const StepArgs &a, const float (&q)
     }
 }
 
-// Gradient step and projection of flow A at voxel v given grad U_A, reading
-// and writing the flow in memory.
-template <int ND, typename T>
-__device__ __forceinline__ void flow_update(const StepArgs &a, int b, int A, int v,
-                                            const float (&G)[3], const bool (&h)[3]) {
-    const size_t V = (size_t)a.V;
-    const size_t base = ((size_t)b * a.nn + A) * ND * V + v;
-    const T *qa = static_cast<const T *>(a.q_in) + base;
-    T *qo = static_cast<T *>(a.q_out) + base;
-    float q[ND], p[ND];
-#pragma unroll
-    for (int k = 0; k < ND; ++k) q[k] = ld(qa, k * V);
-    flow_project<ND>(a, q, G, h, smooth(a, b, A, v), p);
-#pragma unroll
-    for (int k = 0; k < ND; ++k) st(qo, k * V, p[k]);
-}
-
 // Top-down flow excess in path-weight form: d_L += W[A][L] * div q_A
-// (identity for Potts).
+// (identity for Potts).  W is zero for nodes and leaves outside the graph,
+// so no guards are needed.
 template <int NLMAX, bool IDENT>
 __device__ __forceinline__ void add_excess(const StepArgs &a, float (&d)[NLMAX], int A, float dv) {
     if constexpr (IDENT) {
         d[A] += dv;
     } else {
 #pragma unroll
+        for (int L = 0; L < NLMAX; ++L) d[L] = fmaf(wgt(a, A, L), dv, d[L]);
+    }
+}
+
+// grad U_A = sum_L W[A][L] grad u_L (identity for Potts).
+template <int ND, int NLMAX, bool IDENT>
+__device__ __forceinline__ void grad_U(const StepArgs &a, int A, const float (&gu)[NLMAX][ND],
+                                       float (&G)[3]) {
+    G[0] = G[1] = G[2] = 0.f;
+    if constexpr (IDENT) {
+#pragma unroll
+        for (int k = 0; k < ND; ++k) G[k] = gu[A][k];
+    } else {
+#pragma unroll
         for (int L = 0; L < NLMAX; ++L) {
-            if (L < a.nl) {
-                const float w = wgt(a, A, L);
-                if (w != 0.f) d[L] = fmaf(w, dv, d[L]);
-            }
+            const float w = wgt(a, A, L);
+#pragma unroll
+            for (int k = 0; k < ND; ++k) G[k] = fmaf(w, gu[L][k], G[k]);
         }
     }
 }
 
 // Entropic proximal (Bregman) label step in the log domain:
 // ell_L <- (t_L - m) - ln sum_L' exp(t_L' - m),  t_L = ell_L - d_L / c,  m = max t.
+// Slots L >= nl hold copies of a valid label and are masked to -inf.
 template <int NLMAX>
 __device__ __forceinline__ void entropic_step(const StepArgs &a, const float (&d)[NLMAX],
                                               float (&ell)[NLMAX]) {
     float m = -INFINITY;
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L) {
-        if (L < a.nl) {
-            ell[L] = fmaf(-d[L], a.inv_c, ell[L]);
-            m = fmaxf(m, ell[L]);
-        }
+        ell[L] = L < a.nl ? fmaf(-d[L], a.inv_c, ell[L]) : -INFINITY;
+        m = fmaxf(m, ell[L]);
     }
     float s = 0.f;
 #pragma unroll
-    for (int L = 0; L < NLMAX; ++L)
-        if (L < a.nl) s += __expf(ell[L] - m);
+    for (int L = 0; L < NLMAX; ++L) s += __expf(ell[L] - m);
     const float ls = __logf(s);
 #pragma unroll
-    for (int L = 0; L < NLMAX; ++L)
-        if (L < a.nl) ell[L] = (ell[L] - m) - ls;
-}
-
-// grad U_A for every flow A from the leaf gradients gu (path-weight form)
-// and the projected gradient step of each flow at voxel v.
-template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
-__device__ __forceinline__ void flows_from_leaf_gradients(const StepArgs &a, int b, int v,
-                                                          const float (&gu)[NLMAX][ND],
-                                                          const bool (&h)[3]) {
-#pragma unroll
-    for (int A = 0; A < NNMAX; ++A) {
-        if (A < a.nn) {
-            float G[3] = {0.f, 0.f, 0.f};
-            if constexpr (IDENT) {
-#pragma unroll
-                for (int k = 0; k < ND; ++k) G[k] = gu[A][k];
-            } else {
-#pragma unroll
-                for (int L = 0; L < NLMAX; ++L) {
-                    if (L < a.nl) {
-                        const float w = wgt(a, A, L);
-                        if (w != 0.f) {
-#pragma unroll
-                            for (int k = 0; k < ND; ++k) G[k] = fmaf(w, gu[L][k], G[k]);
-                        }
-                    }
-                }
-            }
-            flow_update<ND, T>(a, b, A, v, G, h);
-        }
-    }
+    for (int L = 0; L < NLMAX; ++L) ell[L] = (ell[L] - m) - ls;
 }
 
 }  // namespace dev

@@ -39,7 +39,7 @@ constexpr int FTHREADS = FTX * (FTY + 1);
 // flow one plane below (ignored at z == 0).  Returns the new labels as the
 // exponential of the stored-precision log-label (what the two-pass flow
 // kernel reads back), the old flows at the voxel in qpt, and stores the new
-// log-labels when `store`.
+// log-labels when `store`.  All loads are issued first, unconditionally.
 template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
 __device__ __forceinline__ void label_point(const StepArgs &a, int b, int x, int y, int z,
                                             const float (&qzb)[NNMAX], bool store,
@@ -48,40 +48,39 @@ __device__ __forceinline__ void label_point(const StepArgs &a, int b, int x, int
     const int v = (z * a.ny + y) * a.nx + x;
     const T *q = static_cast<const T *>(a.q_in);
     const T *ell = static_cast<const T *>(a.ell_in);
-    float d[NLMAX], e[NLMAX];
+    const Coord c{x, y, z};
+    int m[3];
+    bool bwd[3];
+    backward_offsets(c, a, m, bwd);
+    const bool fwd[3] = {x < a.nx - 1, y < a.ny - 1, ND == 3 && z < a.nz - 1};
+    float d[NLMAX], e[NLMAX], qm[NNMAX][3];
 #pragma unroll
-    for (int L = 0; L < NLMAX; ++L)
-        if (L < a.nl) d[L] = a.D[((size_t)b * a.nl + L) * V + v];
-#pragma unroll
-    for (int A = 0; A < NNMAX; ++A) {
-        if (A < a.nn) {
-            const T *qa = q + ((size_t)b * a.nn + A) * ND * V;
-#pragma unroll
-            for (int k = 0; k < ND; ++k) qpt[A][k] = ld(qa, k * V + v);
-            // same order of operations as dev::divergence
-            float dv = 0.f;
-            if (x < a.nx - 1) dv += qpt[A][0];
-            if (x > 0) dv -= ld(qa, v - 1);
-            if (y < a.ny - 1) dv += qpt[A][1];
-            if (y > 0) dv -= ld(qa + V, v - a.nx);
-            if constexpr (ND == 3) {
-                if (z < a.nz - 1) dv += qpt[A][2];
-                if (z > 0) dv -= qzb[A];
-            }
-            add_excess<NLMAX, IDENT>(a, d, A, dv);
-        }
+    for (int L = 0; L < NLMAX; ++L) {
+        const int Lc = L < a.nl ? L : a.nl - 1;
+        d[L] = a.D[((size_t)b * a.nl + Lc) * V + v];
+        e[L] = ld(ell, ((size_t)b * a.nl + Lc) * V + v);
     }
 #pragma unroll
-    for (int L = 0; L < NLMAX; ++L)
-        if (L < a.nl) e[L] = ld(ell, ((size_t)b * a.nl + L) * V + v);
+    for (int A = 0; A < NNMAX; ++A) {
+        const int Ac = A < a.nn ? A : a.nn - 1;
+        const T *qa = q + ((size_t)b * a.nn + Ac) * ND * V;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) qpt[A][k] = ld(qa, k * V + v);
+        qm[A][0] = ld(qa, v - m[0]);
+        qm[A][1] = ld(qa + V, v - m[1]);
+        qm[A][2] = ND == 3 ? qzb[A] : 0.f;
+    }
+#pragma unroll
+    for (int A = 0; A < NNMAX; ++A) {
+        const float q0[3] = {qpt[A][0], qpt[A][1], ND == 3 ? qpt[A][ND - 1] : 0.f};
+        add_excess<NLMAX, IDENT>(a, d, A, div_from<ND>(q0, qm[A], fwd, bwd));
+    }
     entropic_step<NLMAX>(a, d, e);
     T *out = static_cast<T *>(a.ell_out);
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L) {
-        if (L < a.nl) {
-            if (store) st(out, ((size_t)b * a.nl + L) * V + v, e[L]);
-            u[L] = __expf(roundtrip(e[L], static_cast<const T *>(nullptr)));
-        }
+        if (store && L < a.nl) st(out, ((size_t)b * a.nl + L) * V + v, e[L]);
+        u[L] = __expf(roundtrip(e[L], static_cast<const T *>(nullptr)));
     }
 }
 
@@ -121,88 +120,77 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
     float ua[NLMAX], ub[NLMAX];
     float qa[NNMAX][ND], qb[NNMAX][ND];
     float qzb[NNMAX];
+#pragma unroll
+    for (int A = 0; A < NNMAX; ++A) qzb[A] = 0.f;
 
     // prologue: labels of plane zs (point A and B), old q_z of plane zs - 1
     if (va) {
         if (ND == 3 && zs > 0) {
             const int vbelow = ((zs - 1) * a.ny + ya) * a.nx + xa;
 #pragma unroll
-            for (int A = 0; A < NNMAX; ++A)
-                if (A < a.nn) qzb[A] = ld(q, (((size_t)b * a.nn + A) * ND + 2) * V + vbelow);
+            for (int A = 0; A < NNMAX; ++A) {
+                const int Ac = A < a.nn ? A : a.nn - 1;
+                qzb[A] = ld(q, (((size_t)b * a.nn + Ac) * ND + 2) * V + vbelow);
+            }
         }
         label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xa, ya, zs, qzb, own, ua, qa);
 #pragma unroll
-        for (int L = 0; L < NLMAX; ++L)
-            if (L < a.nl) lds[L][wave][lane] = ua[L];
+        for (int L = 0; L < NLMAX; ++L) lds[L][wave][lane] = ua[L];
     }
     if (vb) {
         if (ND == 3 && zs > 0) {
             const int vbelow = ((zs - 1) * a.ny + yb) * a.nx + xb;
 #pragma unroll
-            for (int A = 0; A < NNMAX; ++A)
-                if (A < a.nn) qzb[A] = ld(q, (((size_t)b * a.nn + A) * ND + 2) * V + vbelow);
+            for (int A = 0; A < NNMAX; ++A) {
+                const int Ac = A < a.nn ? A : a.nn - 1;
+                qzb[A] = ld(q, (((size_t)b * a.nn + Ac) * ND + 2) * V + vbelow);
+            }
         }
         label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xb, yb, zs, qzb, false, ub, qb);
 #pragma unroll
-        for (int L = 0; L < NLMAX; ++L)
-            if (L < a.nl) lds[L][lane][FTX] = ub[L];
+        for (int L = 0; L < NLMAX; ++L) lds[L][lane][FTX] = ub[L];
     }
     __syncthreads();
 
     for (int z = zs; z < ze; ++z) {
         const bool has_next = z + 1 < a.nz;
-        float un[NLMAX], qn[NNMAX][ND];
+        float un[NLMAX], qn[NNMAX][ND], ubn[NLMAX];
+#pragma unroll
+        for (int L = 0; L < NLMAX; ++L) un[L] = ubn[L] = ua[L];   // defined when !has_next
         // labels of plane z + 1 (owned when z + 1 < ze, else the halo plane)
         if (va && has_next) {
             float qz[NNMAX];
 #pragma unroll
-            for (int A = 0; A < NNMAX; ++A)
-                if (A < a.nn) qz[A] = qa[A][ND - 1];
+            for (int A = 0; A < NNMAX; ++A) qz[A] = qa[A][ND - 1];
             label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xa, ya, z + 1, qz, own && z + 1 < ze,
                                                     un, qn);
         }
-        float ubn[NLMAX];
         if (vb && has_next) {
             float qz[NNMAX];
 #pragma unroll
-            for (int A = 0; A < NNMAX; ++A)
-                if (A < a.nn) qz[A] = qb[A][ND - 1];
+            for (int A = 0; A < NNMAX; ++A) qz[A] = qb[A][ND - 1];
             label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xb, yb, z + 1, qz, false, ubn, qb);
         }
         // flow step of the owned voxels of plane z
         if (own) {
             const int v = (z * a.ny + ya) * a.nx + xa;
             const bool h[3] = {xa < a.nx - 1, ya < a.ny - 1, ND == 3 && has_next};
+            float sv[NNMAX];
+#pragma unroll
+            for (int A = 0; A < NNMAX; ++A) sv[A] = smooth(a, b, A < a.nn ? A : a.nn - 1, v);
             float gu[NLMAX][ND];
 #pragma unroll
             for (int L = 0; L < NLMAX; ++L) {
-                if (L < a.nl) {
-                    gu[L][0] = h[0] ? lds[L][wave][lane + 1] - ua[L] : 0.f;
-                    gu[L][1] = h[1] ? lds[L][wave + 1][lane] - ua[L] : 0.f;
-                    if constexpr (ND == 3) gu[L][2] = h[2] ? un[L] - ua[L] : 0.f;
-                }
+                gu[L][0] = h[0] ? lds[L][wave][lane + 1] - ua[L] : 0.f;
+                gu[L][1] = h[1] ? lds[L][wave + 1][lane] - ua[L] : 0.f;
+                if constexpr (ND == 3) gu[L][2] = h[2] ? un[L] - ua[L] : 0.f;
             }
 #pragma unroll
             for (int A = 0; A < NNMAX; ++A) {
                 if (A < a.nn) {
-                    float G[3] = {0.f, 0.f, 0.f};
-                    if constexpr (IDENT) {
-#pragma unroll
-                        for (int k = 0; k < ND; ++k) G[k] = gu[A][k];
-                    } else {
-#pragma unroll
-                        for (int L = 0; L < NLMAX; ++L) {
-                            if (L < a.nl) {
-                                const float w = wgt(a, A, L);
-                                if (w != 0.f) {
-#pragma unroll
-                                    for (int k = 0; k < ND; ++k) G[k] = fmaf(w, gu[L][k], G[k]);
-                                }
-                            }
-                        }
-                    }
-                    float p[ND];
-                    flow_project<ND>(a, qa[A], G, h, smooth(a, b, A, v), p);
+                    float G[3], p[ND];
+                    grad_U<ND, NLMAX, IDENT>(a, A, gu, G);
+                    flow_project<ND>(a, qa[A], G, h, sv[A], p);
                     T *qo = qout + ((size_t)b * a.nn + A) * ND * V + v;
 #pragma unroll
                     for (int k = 0; k < ND; ++k) st(qo, k * V, p[k]);
@@ -214,21 +202,17 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
             if (va) {
 #pragma unroll
                 for (int L = 0; L < NLMAX; ++L) {
-                    if (L < a.nl) {
-                        lds[L][wave][lane] = un[L];
-                        ua[L] = un[L];
-                    }
+                    lds[L][wave][lane] = un[L];
+                    ua[L] = un[L];
                 }
 #pragma unroll
                 for (int A = 0; A < NNMAX; ++A)
 #pragma unroll
-                    for (int k = 0; k < ND; ++k)
-                        if (A < a.nn) qa[A][k] = qn[A][k];
+                    for (int k = 0; k < ND; ++k) qa[A][k] = qn[A][k];
             }
             if (vb) {
 #pragma unroll
-                for (int L = 0; L < NLMAX; ++L)
-                    if (L < a.nl) lds[L][lane][FTX] = ubn[L];
+                for (int L = 0; L < NLMAX; ++L) lds[L][lane][FTX] = ubn[L];
             }
         }
         __syncthreads();

@@ -37,21 +37,33 @@ __device__ __forceinline__ void label_body(const StepArgs &a) {
     const T *q = static_cast<const T *>(a.q_in);
     const T *ell = static_cast<const T *>(a.ell_in);
     T *out = static_cast<T *>(a.ell_out);
+    int m[3];
+    bool bwd[3];
+    backward_offsets(c, a, m, bwd);
+    const bool fwd[3] = {c.x < a.nx - 1, c.y < a.ny - 1, ND == 3 && c.z < a.nz - 1};
 
-    float d[NLMAX], e[NLMAX];
+    // load phase: every load unconditional, indices clamped into the volume
+    // and into the label / node ranges
+    float d[NLMAX], e[NLMAX], q0[NNMAX][3], qm[NNMAX][3];
 #pragma unroll
-    for (int L = 0; L < NLMAX; ++L)
-        if (L < a.nl) d[L] = a.D[((size_t)b * a.nl + L) * V + v];
-#pragma unroll
-    for (int A = 0; A < NNMAX; ++A) {
-        if (A < a.nn) {
-            const T *qa = q + ((size_t)b * a.nn + A) * ND * V;
-            add_excess<NLMAX, IDENT>(a, d, A, divergence<ND>(qa, V, v, c, a));
-        }
+    for (int L = 0; L < NLMAX; ++L) {
+        const int Lc = L < a.nl ? L : a.nl - 1;
+        d[L] = a.D[((size_t)b * a.nl + Lc) * V + v];
+        e[L] = ld(ell, ((size_t)b * a.nl + Lc) * V + v);
     }
 #pragma unroll
-    for (int L = 0; L < NLMAX; ++L)
-        if (L < a.nl) e[L] = ld(ell, ((size_t)b * a.nl + L) * V + v);
+    for (int A = 0; A < NNMAX; ++A) {
+        const int Ac = A < a.nn ? A : a.nn - 1;
+        const T *qa = q + ((size_t)b * a.nn + Ac) * ND * V;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) {
+            q0[A][k] = ld(qa, k * V + v);
+            qm[A][k] = ld(qa, k * V + v - m[k]);
+        }
+    }
+    // compute phase
+#pragma unroll
+    for (int A = 0; A < NNMAX; ++A) add_excess<NLMAX, IDENT>(a, d, A, div_from<ND>(q0[A], qm[A], fwd, bwd));
     entropic_step<NLMAX>(a, d, e);
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L)
@@ -73,20 +85,50 @@ __device__ __forceinline__ void flow_body(const StepArgs &a) {
     const Coord c = coord_of(v, a.nx, a.ny);
     const size_t V = (size_t)a.V;
     const T *ell = static_cast<const T *>(a.ell_in);
+    const T *q = static_cast<const T *>(a.q_in);
+    T *qout = static_cast<T *>(a.q_out);
     const bool h[3] = {c.x < a.nx - 1, c.y < a.ny - 1, ND == 3 && c.z < a.nz - 1};
-    const int off[3] = {1, a.nx, a.nx * a.ny};
+    // forward offsets, 0 on the last index so that the loads stay in the volume
+    const int off[3] = {h[0] ? 1 : 0, h[1] ? a.nx : 0, h[2] ? a.nx * a.ny : 0};
 
+    // load phase
+    float e0[NLMAX], en[NLMAX][ND], qv[NNMAX][ND], sv[NNMAX];
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L) {
+        const int Lc = L < a.nl ? L : a.nl - 1;
+        const size_t base = ((size_t)b * a.nl + Lc) * V + v;
+        e0[L] = ld(ell, base);
+#pragma unroll
+        for (int k = 0; k < ND; ++k) en[L][k] = ld(ell, base + off[k]);
+    }
+#pragma unroll
+    for (int A = 0; A < NNMAX; ++A) {
+        const int Ac = A < a.nn ? A : a.nn - 1;
+        const T *qa = q + ((size_t)b * a.nn + Ac) * ND * V;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) qv[A][k] = ld(qa, k * V + v);
+        sv[A] = smooth(a, b, Ac, v);
+    }
+    // compute phase: labels u = exp(ell), their forward differences, the
+    // implicit-label gradients and the projected flow steps
     float gu[NLMAX][ND];
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L) {
-        if (L < a.nl) {
-            const T *e = ell + ((size_t)b * a.nl + L) * V + v;
-            const float u0 = __expf(ld(e, 0));
+        const float u0 = __expf(e0[L]);
 #pragma unroll
-            for (int k = 0; k < ND; ++k) gu[L][k] = h[k] ? __expf(ld(e, off[k])) - u0 : 0.f;
+        for (int k = 0; k < ND; ++k) gu[L][k] = h[k] ? __expf(en[L][k]) - u0 : 0.f;
+    }
+#pragma unroll
+    for (int A = 0; A < NNMAX; ++A) {
+        if (A < a.nn) {
+            float G[3], p[ND];
+            grad_U<ND, NLMAX, IDENT>(a, A, gu, G);
+            flow_project<ND>(a, qv[A], G, h, sv[A], p);
+            T *qo = qout + ((size_t)b * a.nn + A) * ND * V + v;
+#pragma unroll
+            for (int k = 0; k < ND; ++k) st(qo, k * V, p[k]);
         }
     }
-    flows_from_leaf_gradients<ND, NLMAX, NNMAX, IDENT, T>(a, b, v, gu, h);
 }
 
 template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
