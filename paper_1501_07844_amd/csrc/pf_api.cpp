@@ -96,9 +96,10 @@ int check_grid(const pf_grid *g) {
                     g->nz, g->ny, g->nx);
     if (g->ndim == 2 && g->nz != 1) return fail(PF_EINVAL, "ndim == 2 requires nz == 1 (got %d)", g->nz);
     if (g->batch > 65535) return fail(PF_EUNSUPPORTED, "batch > 65535");
+    // byte offsets of 4-byte fields inside one problem stay below 2^32
     const double V = (double)g->nx * g->ny * g->nz;
-    if (V > 2147483647.0 - 2.0 * g->nx * g->ny)
-        return fail(PF_EUNSUPPORTED, "more than 2^31 voxels per problem");
+    if (V > 1073741824.0 - 2.0 * g->nx * g->ny)
+        return fail(PF_EUNSUPPORTED, "more than 2^30 voxels per problem");
     return PF_OK;
 }
 

@@ -53,6 +53,36 @@ __device__ __forceinline__ float wgt(const StepArgs &a, int A, int L) {
 
 // ------------------------------------------------------------ helpers ----
 
+// Start of field f of problem b in a [B][F][V] array: uniform across the
+// block, so that loads become "uniform base + 32-bit lane offset" (the
+// global saddr form, one offset VGPR shared by every field of a voxel).
+template <typename T>
+__device__ __forceinline__ const T *field(const void *base, int b, int nf, int f, size_t V) {
+    return static_cast<const T *>(base) + ((size_t)b * nf + f) * V;
+}
+template <typename T>
+__device__ __forceinline__ T *field_w(void *base, int b, int nf, int f, size_t V) {
+    return static_cast<T *>(base) + ((size_t)b * nf + f) * V;
+}
+
+// Load / store at a 32-bit byte offset from a uniform base.  Voxels per
+// problem are capped at 2^30 by the host checks, so offsets of 4-byte
+// fields fit in 32 bits; the explicit 32-bit offset lets the compiler use
+// one shared offset VGPR with the base in SGPRs.
+template <typename T>
+__device__ __forceinline__ float ldo(const T *base, unsigned idx) {
+    return ld(reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) +
+                                          (unsigned)(idx * (unsigned)sizeof(T))), 0);
+}
+template <typename T>
+__device__ __forceinline__ void sto(T *base, unsigned idx, float v) {
+    st(reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (unsigned)(idx * (unsigned)sizeof(T))),
+       0, v);
+}
+__device__ __forceinline__ float ldf(const float *base, unsigned idx) {
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + idx * 4u);
+}
+
 struct Coord {
     int x, y, z;
 };
@@ -72,7 +102,8 @@ __device__ __forceinline__ Coord coord_of(int v, int nx, int ny) {
 // feeding the following flow address was read from a register that path never
 // wrote.  The branch-free form leaves no such path.)
 __device__ __forceinline__ float smooth(const StepArgs &a, int b, int A, int v) {
-    return a.Sp[(int64_t)b * a.s_sb + (int64_t)A * a.s_sa + (int64_t)v * a.s_sv];
+    const float *base = a.Sp + ((int64_t)b * a.s_sb + (int64_t)A * a.s_sa);
+    return ldf(base, (unsigned)v * (unsigned)a.s_sv);
 }
 
 // div q_A from the flow components at x (q0) and at x - e_k (qm):

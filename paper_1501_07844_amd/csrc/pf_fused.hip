@@ -46,8 +46,7 @@ __device__ __forceinline__ void label_point(const StepArgs &a, int b, int x, int
                                             float (&u)[NLMAX], float (&qpt)[NNMAX][ND]) {
     const size_t V = (size_t)a.V;
     const int v = (z * a.ny + y) * a.nx + x;
-    const T *q = static_cast<const T *>(a.q_in);
-    const T *ell = static_cast<const T *>(a.ell_in);
+    const unsigned uv = (unsigned)v;
     const Coord c{x, y, z};
     int m[3];
     bool bwd[3];
@@ -57,17 +56,19 @@ __device__ __forceinline__ void label_point(const StepArgs &a, int b, int x, int
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L) {
         const int Lc = L < a.nl ? L : a.nl - 1;
-        d[L] = a.D[((size_t)b * a.nl + Lc) * V + v];
-        e[L] = ld(ell, ((size_t)b * a.nl + Lc) * V + v);
+        d[L] = ldf(field<float>(a.D, b, a.nl, Lc, V), uv);
+        e[L] = ldo(field<T>(a.ell_in, b, a.nl, Lc, V), uv);
     }
 #pragma unroll
     for (int A = 0; A < NNMAX; ++A) {
         const int Ac = A < a.nn ? A : a.nn - 1;
-        const T *qa = q + ((size_t)b * a.nn + Ac) * ND * V;
-#pragma unroll
-        for (int k = 0; k < ND; ++k) qpt[A][k] = ld(qa, k * V + v);
-        qm[A][0] = ld(qa, v - m[0]);
-        qm[A][1] = ld(qa + V, v - m[1]);
+        const T *qx = field<T>(a.q_in, b, a.nn * ND, Ac * ND, V);
+        const T *qy = field<T>(a.q_in, b, a.nn * ND, Ac * ND + 1, V);
+        qpt[A][0] = ldo(qx, uv);
+        qpt[A][1] = ldo(qy, uv);
+        if constexpr (ND == 3) qpt[A][2] = ldo(field<T>(a.q_in, b, a.nn * ND, Ac * ND + 2, V), uv);
+        qm[A][0] = ldo(qx, uv - (unsigned)m[0]);
+        qm[A][1] = ldo(qy, uv - (unsigned)m[1]);
         qm[A][2] = ND == 3 ? qzb[A] : 0.f;
     }
 #pragma unroll
@@ -76,10 +77,9 @@ __device__ __forceinline__ void label_point(const StepArgs &a, int b, int x, int
         add_excess<NLMAX, IDENT>(a, d, A, div_from<ND>(q0, qm[A], fwd, bwd));
     }
     entropic_step<NLMAX>(a, d, e);
-    T *out = static_cast<T *>(a.ell_out);
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L) {
-        if (store && L < a.nl) st(out, ((size_t)b * a.nl + L) * V + v, e[L]);
+        if (store && L < a.nl) sto(field_w<T>(a.ell_out, b, a.nl, L, V), uv, e[L]);
         u[L] = __expf(roundtrip(e[L], static_cast<const T *>(nullptr)));
     }
 }
@@ -114,8 +114,6 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
     const bool vb = halo && lane < FTY && xb < a.nx && yb < a.ny;
 
     const size_t V = (size_t)a.V;
-    const T *q = static_cast<const T *>(a.q_in);
-    T *qout = static_cast<T *>(a.q_out);
 
     float ua[NLMAX], ub[NLMAX];
     float qa[NNMAX][ND], qb[NNMAX][ND];
@@ -130,7 +128,7 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
 #pragma unroll
             for (int A = 0; A < NNMAX; ++A) {
                 const int Ac = A < a.nn ? A : a.nn - 1;
-                qzb[A] = ld(q, (((size_t)b * a.nn + Ac) * ND + 2) * V + vbelow);
+                qzb[A] = ldo(field<T>(a.q_in, b, a.nn * ND, Ac * ND + 2, V), (unsigned)vbelow);
             }
         }
         label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xa, ya, zs, qzb, own, ua, qa);
@@ -143,7 +141,7 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
 #pragma unroll
             for (int A = 0; A < NNMAX; ++A) {
                 const int Ac = A < a.nn ? A : a.nn - 1;
-                qzb[A] = ld(q, (((size_t)b * a.nn + Ac) * ND + 2) * V + vbelow);
+                qzb[A] = ldo(field<T>(a.q_in, b, a.nn * ND, Ac * ND + 2, V), (unsigned)vbelow);
             }
         }
         label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xb, yb, zs, qzb, false, ub, qb);
@@ -191,9 +189,9 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
                     float G[3], p[ND];
                     grad_U<ND, NLMAX, IDENT>(a, A, gu, G);
                     flow_project<ND>(a, qa[A], G, h, sv[A], p);
-                    T *qo = qout + ((size_t)b * a.nn + A) * ND * V + v;
 #pragma unroll
-                    for (int k = 0; k < ND; ++k) st(qo, k * V, p[k]);
+                    for (int k = 0; k < ND; ++k)
+                        sto(field_w<T>(a.q_out, b, a.nn * ND, A * ND + k, V), (unsigned)v, p[k]);
                 }
             }
         }

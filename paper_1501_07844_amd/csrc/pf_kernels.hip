@@ -34,31 +34,29 @@ __device__ __forceinline__ void label_body(const StepArgs &a) {
     const int b = blockIdx.y;
     const Coord c = coord_of(v, a.nx, a.ny);
     const size_t V = (size_t)a.V;
-    const T *q = static_cast<const T *>(a.q_in);
-    const T *ell = static_cast<const T *>(a.ell_in);
-    T *out = static_cast<T *>(a.ell_out);
     int m[3];
     bool bwd[3];
     backward_offsets(c, a, m, bwd);
     const bool fwd[3] = {c.x < a.nx - 1, c.y < a.ny - 1, ND == 3 && c.z < a.nz - 1};
 
     // load phase: every load unconditional, indices clamped into the volume
-    // and into the label / node ranges
+    // and into the label / node ranges; uniform field bases + 32-bit offsets
+    const unsigned uv = (unsigned)v;
     float d[NLMAX], e[NLMAX], q0[NNMAX][3], qm[NNMAX][3];
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L) {
         const int Lc = L < a.nl ? L : a.nl - 1;
-        d[L] = a.D[((size_t)b * a.nl + Lc) * V + v];
-        e[L] = ld(ell, ((size_t)b * a.nl + Lc) * V + v);
+        d[L] = ldf(field<float>(a.D, b, a.nl, Lc, V), uv);
+        e[L] = ldo(field<T>(a.ell_in, b, a.nl, Lc, V), uv);
     }
 #pragma unroll
     for (int A = 0; A < NNMAX; ++A) {
         const int Ac = A < a.nn ? A : a.nn - 1;
-        const T *qa = q + ((size_t)b * a.nn + Ac) * ND * V;
 #pragma unroll
         for (int k = 0; k < ND; ++k) {
-            q0[A][k] = ld(qa, k * V + v);
-            qm[A][k] = ld(qa, k * V + v - m[k]);
+            const T *qk = field<T>(a.q_in, b, a.nn * ND, Ac * ND + k, V);
+            q0[A][k] = ldo(qk, uv);
+            qm[A][k] = ldo(qk, uv - (unsigned)m[k]);
         }
     }
     // compute phase
@@ -67,7 +65,7 @@ __device__ __forceinline__ void label_body(const StepArgs &a) {
     entropic_step<NLMAX>(a, d, e);
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L)
-        if (L < a.nl) st(out, ((size_t)b * a.nl + L) * V + v, e[L]);
+        if (L < a.nl) sto(field_w<T>(a.ell_out, b, a.nl, L, V), uv, e[L]);
 }
 
 template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
@@ -84,29 +82,26 @@ __device__ __forceinline__ void flow_body(const StepArgs &a) {
     const int b = blockIdx.y;
     const Coord c = coord_of(v, a.nx, a.ny);
     const size_t V = (size_t)a.V;
-    const T *ell = static_cast<const T *>(a.ell_in);
-    const T *q = static_cast<const T *>(a.q_in);
-    T *qout = static_cast<T *>(a.q_out);
     const bool h[3] = {c.x < a.nx - 1, c.y < a.ny - 1, ND == 3 && c.z < a.nz - 1};
     // forward offsets, 0 on the last index so that the loads stay in the volume
     const int off[3] = {h[0] ? 1 : 0, h[1] ? a.nx : 0, h[2] ? a.nx * a.ny : 0};
 
-    // load phase
+    // load phase (uniform field bases + 32-bit lane offsets)
+    const unsigned uv = (unsigned)v;
     float e0[NLMAX], en[NLMAX][ND], qv[NNMAX][ND], sv[NNMAX];
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L) {
         const int Lc = L < a.nl ? L : a.nl - 1;
-        const size_t base = ((size_t)b * a.nl + Lc) * V + v;
-        e0[L] = ld(ell, base);
+        const T *el = field<T>(a.ell_in, b, a.nl, Lc, V);
+        e0[L] = ldo(el, uv);
 #pragma unroll
-        for (int k = 0; k < ND; ++k) en[L][k] = ld(ell, base + off[k]);
+        for (int k = 0; k < ND; ++k) en[L][k] = ldo(el, uv + (unsigned)off[k]);
     }
 #pragma unroll
     for (int A = 0; A < NNMAX; ++A) {
         const int Ac = A < a.nn ? A : a.nn - 1;
-        const T *qa = q + ((size_t)b * a.nn + Ac) * ND * V;
 #pragma unroll
-        for (int k = 0; k < ND; ++k) qv[A][k] = ld(qa, k * V + v);
+        for (int k = 0; k < ND; ++k) qv[A][k] = ldo(field<T>(a.q_in, b, a.nn * ND, Ac * ND + k, V), uv);
         sv[A] = smooth(a, b, Ac, v);
     }
     // compute phase: labels u = exp(ell), their forward differences, the
@@ -124,9 +119,8 @@ __device__ __forceinline__ void flow_body(const StepArgs &a) {
             float G[3], p[ND];
             grad_U<ND, NLMAX, IDENT>(a, A, gu, G);
             flow_project<ND>(a, qv[A], G, h, sv[A], p);
-            T *qo = qout + ((size_t)b * a.nn + A) * ND * V + v;
 #pragma unroll
-            for (int k = 0; k < ND; ++k) st(qo, k * V, p[k]);
+            for (int k = 0; k < ND; ++k) sto(field_w<T>(a.q_out, b, a.nn * ND, A * ND + k, V), uv, p[k]);
         }
     }
 }
