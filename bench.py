@@ -31,7 +31,7 @@ ITERS = 500
 
 def _kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("pf_kernels.hip", "pf_api.cpp", "pf_internal.h"):
+    for f in ("pf_kernels.hip", "pf_fused.hip", "pf_device.h", "pf_api.cpp", "pf_internal.h"):
         with open(os.path.join(ROOT, "paper_1501_07844_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -60,6 +60,7 @@ def main() -> int:
     ap.add_argument("--kernel", default="auto", choices=["auto", "two_pass", "fused"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
@@ -146,11 +147,69 @@ def main() -> int:
             "kernel_avg_ms": round(kmsb / max(knb, 1), 4), "ms_per_step": 1e3 * eb / args.steps}
         print(f"[bench] bf16: {1e3 * eb / args.steps:.1f} ms/step", file=sys.stderr, flush=True)
 
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(dev)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
 
     print(json.dumps(out), flush=True)
     return 0
+
+
+def adjoint_leg(dev, reps: int = 3) -> dict:
+    """Cost of the differentiable solve on its own workload: 16 Potts problems
+    of 256 x 256, 5 labels, 100 unrolled iterations, checkpoint every 10,
+    cross-entropy loss against the ground-truth labels.  Times (HIP events on
+    the stream the library launches on, median of `reps` after one warm-up):
+    the plain forward solve, the recorded forward, and the backward."""
+    import torch
+
+    import paper_1501_07844_amd as pf
+    from paper_1501_07844_amd import synth
+
+    p = synth.diff_batch()
+    D = torch.from_numpy(p.D).to(dev)
+    S = torch.from_numpy(p.S).to(dev)
+    gt = torch.from_numpy(p.gt.astype("int64")).to(dev).unsqueeze(1)
+    k = p.extra["checkpoint_every"]
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1), r
+
+    ws = [None]
+
+    def plain():
+        r = pf.solve_potts(D, S, c=p.c, tau=p.tau, iters=p.iters, s_mode="shared_field", ndim=2,
+                           kernel="two_pass", final_energy=False, return_u=False,
+                           return_labels=False, return_ell=True, workspace=ws[0])
+        ws[0] = r.workspace
+        return r
+
+    f_ms, r_ms, b_ms = [], [], []
+    for i in range(reps + 1):
+        tf, _ = timed(plain)
+        Dg = D.clone().requires_grad_(True)
+        Sg = S.clone().requires_grad_(True)
+        tr, ell = timed(lambda: pf.potts_layer(Dg, Sg, c=p.c, tau=p.tau, iters=p.iters,
+                                               ckpt_every=k))
+        loss = -torch.gather(ell, 1, gt).mean()
+        tb, _ = timed(lambda: loss.backward())
+        if i:
+            f_ms.append(tf), r_ms.append(tr), b_ms.append(tb)
+    med = lambda v: sorted(v)[len(v) // 2]
+    f, r, b = med(f_ms), med(r_ms), med(b_ms)
+    print(f"[bench] adjoint: forward {f:.2f} ms, recorded {r:.2f} ms, backward {b:.2f} ms",
+          file=sys.stderr, flush=True)
+    return {"workload": f"diff_batch 16x256x256, 5 labels, {p.iters} iterations, checkpoint "
+                        f"every {k}, fp32", "forward_ms": round(f, 3),
+            "forward_recorded_ms": round(r, 3), "backward_ms": round(b, 3),
+            "backward_over_forward": round(b / f, 3), "total_over_forward": round((r + b) / f, 3)}
 
 
 def cpu_baseline(p) -> dict:

@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define PF_ABI_VERSION 1
+#define PF_ABI_VERSION 2
 #define PF_MAX_LEAVES 16     /* end-labels per problem */
 #define PF_MAX_NODES 32      /* non-source nodes per problem */
 
@@ -67,7 +67,8 @@ typedef enum {
 } pf_s_mode;
 
 typedef enum {
-    PF_KERNEL_AUTO = 0,      /* fused single pass where available */
+    PF_KERNEL_AUTO = 0,      /* the faster variant as measured on MI355X: fused for 3-D
+                                Potts with fp32 state, two-pass otherwise */
     PF_KERNEL_TWO_PASS = 1,  /* label pass then flow pass, state updated in place */
     PF_KERNEL_FUSED = 2      /* one pass per iteration, state ping-ponged */
 } pf_kernel;
@@ -98,12 +99,20 @@ typedef struct {
     int32_t timing_stride;   /* > 0: time every timing_stride-th iteration with HIP events */
     void *workspace;         /* device, 256-byte aligned, caller-owned */
     size_t workspace_bytes;
+    /* Differentiable solves (float32 state only).  With tape != NULL the
+     * forward solve records the state before every ckpt_every-th iteration
+     * (pf_tape_bytes) for the *_backward entry points; it then runs the
+     * two-pass kernels and needs gap_tol == 0 and warm_start == 0. */
+    int32_t ckpt_every;      /* >= 1 when tape != NULL */
+    void *tape;              /* device, 256-byte aligned, caller-owned, or NULL */
+    size_t tape_bytes;
 } pf_params;
 
 typedef struct {
     float *u;                /* device out [B][n_leaf][Z][Y][X] fp32, or NULL */
     int32_t *labels;         /* device out [B][Z][Y][X] argmax leaf (ties: lowest), or NULL */
     float *q;                /* device out [B][n_node][ndim][Z][Y][X] fp32, or NULL */
+    float *ell;              /* device out [B][n_leaf][Z][Y][X] fp32 log-labels ln u, or NULL */
     double *gap_history;     /* host out [gap_history_cap] absolute gaps, or NULL */
     int32_t gap_history_cap;
     /* filled by the call */
@@ -159,6 +168,34 @@ int solve_hmf(const pf_grid *grid, const pf_graph *graph, const float *D, const 
  * S per s_mode with n_node = N.  Supports PF_KERNEL_TWO_PASS/AUTO. */
 int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
                    int32_t s_mode, const pf_params *params, pf_result *result, void *stream);
+
+/* Bytes of checkpoint tape for `iters` iterations recorded every
+ * `ckpt_every` iterations (float32 state); 0 for invalid arguments. */
+size_t pf_tape_bytes(const pf_grid *grid, int32_t n_leaf, int32_t n_node, int32_t iters,
+                     int32_t ckpt_every);
+
+/* Bytes of device workspace for a backward call (segment states, adjoint
+ * buffers); 0 for invalid arguments. */
+size_t pf_backward_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t n_node,
+                                   int32_t ckpt_every);
+
+/* Reverse-mode gradient of a loss on the final log-labels ell_K = ln u_K of
+ * a recorded solve (the paper has no gradients; this differentiates its
+ * Algorithm 1 / Algorithm 2 iteration as unrolled).  Inputs: the same grid,
+ * labels or graph, D, S and s_mode as the recorded call, and `params` with the
+ * same iters, c, tau, ckpt_every and tape, `workspace` of at least
+ * pf_backward_workspace_bytes.  grad_ell: device float[B][n_leaf][Z][Y][X],
+ * dLoss/d ell_K.  Outputs (device, float32, overwritten): grad_D shaped like
+ * D; grad_S shaped like S for the field modes, float[n_node] on the device for
+ * PF_S_NODE_SCALAR (summed over voxels and problems).  Checkpoint segments
+ * are recomputed with the forward kernels; each reverse step is two kernels
+ * (projection adjoint, then label adjoint). */
+int solve_potts_backward(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
+                         int32_t s_mode, const pf_params *params, const float *grad_ell,
+                         float *grad_D, float *grad_S, void *stream);
+int solve_dagmf_backward(const pf_grid *grid, const pf_graph *graph, const float *D,
+                         const float *S, int32_t s_mode, const pf_params *params,
+                         const float *grad_ell, float *grad_D, float *grad_S, void *stream);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char *pf_last_error(void);

@@ -7,7 +7,10 @@ pointers and torch's current HIP stream.  Every step of the solve runs in the
 library's HIP kernels; there is no CPU fallback, and a missing library raises.
 
 Entry points mirror the C names: ``solve_potts``, ``solve_hmf``,
-``solve_dagmf``, ``solve_ishikawa``, ``workspace_bytes``.
+``solve_dagmf``, ``solve_ishikawa``, ``workspace_bytes``, ``tape_bytes``.
+``potts_layer`` and ``dagmf_layer`` wrap a recorded solve and the C backward
+entry points in a ``torch.autograd.Function``: the loss gradient on the final
+log-labels flows back to the data terms and the capacities.
 """
 from __future__ import annotations
 
@@ -20,6 +23,7 @@ import numpy as np
 
 __all__ = [
     "solve_potts", "solve_hmf", "solve_dagmf", "solve_ishikawa", "workspace_bytes",
+    "potts_layer", "dagmf_layer", "tape_bytes",
     "SolveResult", "PseudoflowError", "library", "lib_path", "EXPORTED",
     "PF_OK", "PF_EINVAL", "PF_EGRAPH", "PF_ENOMEM", "PF_EHIP", "PF_ENONFINITE",
     "PF_EUNSUPPORTED", "MAX_LEAVES", "MAX_NODES",
@@ -33,7 +37,9 @@ S_MODE = {"node_scalar": 0, "shared_field": 1, "node_field": 2}
 
 # every symbol include/pseudoflow.h declares
 EXPORTED = ["pf_workspace_bytes", "solve_potts", "solve_dagmf", "solve_hmf",
-            "solve_ishikawa", "pf_last_error", "pf_abi_version"]
+            "solve_ishikawa", "pf_last_error", "pf_abi_version", "pf_tape_bytes",
+            "pf_backward_workspace_bytes", "solve_potts_backward", "solve_dagmf_backward"]
+ABI_VERSION = 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -65,11 +71,12 @@ class _Params(C.Structure):
                 ("gap_every", C.c_int32), ("gap_tol", C.c_double),
                 ("final_energy", C.c_int32), ("check_inputs", C.c_int32),
                 ("timing_stride", C.c_int32), ("workspace", C.c_void_p),
-                ("workspace_bytes", C.c_size_t)]
+                ("workspace_bytes", C.c_size_t), ("ckpt_every", C.c_int32),
+                ("tape", C.c_void_p), ("tape_bytes", C.c_size_t)]
 
 
 class _Result(C.Structure):
-    _fields_ = [("u", C.c_void_p), ("labels", C.c_void_p), ("q", C.c_void_p),
+    _fields_ = [("u", C.c_void_p), ("labels", C.c_void_p), ("q", C.c_void_p), ("ell", C.c_void_p),
                 ("gap_history", C.POINTER(C.c_double)), ("gap_history_cap", C.c_int32),
                 ("gap_history_len", C.c_int32), ("iters_done", C.c_int32),
                 ("energy", C.c_double), ("dual", C.c_double), ("gap", C.c_double),
@@ -103,6 +110,20 @@ def library() -> C.CDLL:
             f.argtypes = argt
         lib.pf_last_error.restype = C.c_char_p
         lib.pf_abi_version.restype = C.c_int32
+        lib.pf_tape_bytes.restype = C.c_size_t
+        lib.pf_tape_bytes.argtypes = [C.POINTER(_Grid), C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+        lib.pf_backward_workspace_bytes.restype = C.c_size_t
+        lib.pf_backward_workspace_bytes.argtypes = [C.POINTER(_Grid), C.c_int32, C.c_int32, C.c_int32]
+        bsig = [C.POINTER(_Grid), C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(_Params),
+                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        bgsig = [C.POINTER(_Grid), C.POINTER(_Graph), C.c_void_p, C.c_void_p, C.c_int32,
+                 C.POINTER(_Params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.solve_potts_backward.restype = C.c_int
+        lib.solve_potts_backward.argtypes = bsig
+        lib.solve_dagmf_backward.restype = C.c_int
+        lib.solve_dagmf_backward.argtypes = bgsig
+        if lib.pf_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"{path}: ABI {lib.pf_abi_version()} != {ABI_VERSION}; rebuild it")
         _LIB = lib
     return _LIB
 
@@ -110,6 +131,7 @@ def library() -> C.CDLL:
 @dataclass
 class SolveResult:
     u: Optional[object]            # torch float32 [B][n_leaf][Z][Y][X]
+    ell: Optional[object]          # torch float32 [B][n_leaf][Z][Y][X], ln u
     labels: Optional[object]       # torch int32 [B][Z][Y][X]
     q: Optional[object]            # torch float32 [B][n_node][ndim][Z][Y][X]
     iters_done: int
@@ -192,8 +214,8 @@ def _graph_struct(graph, keep) -> _Graph:
 def _solve(entry, D, S, n_leaf, n_node, *, graph=None, n_labels=None, c, tau, iters,
            s_mode=None, ndim=None, storage="fp32", kernel="auto", gap_every=0, gap_tol=0.0,
            final_energy=True, check_inputs=False, timing_stride=0, return_u=True,
-           return_labels=True, return_q=False, workspace=None, warm_start=False,
-           gap_history_cap=0) -> SolveResult:
+           return_labels=True, return_q=False, return_ell=False, workspace=None,
+           warm_start=False, gap_history_cap=0, tape=None, ckpt_every=0) -> SolveResult:
     torch = _torch()
     lib = library()
     _check_dev(D, "D", torch.float32)
@@ -207,6 +229,8 @@ def _solve(entry, D, S, n_leaf, n_node, *, graph=None, n_labels=None, c, tau, it
     p.warm_start, p.gap_every, p.gap_tol = int(bool(warm_start)), int(gap_every), float(gap_tol)
     p.final_energy, p.check_inputs = int(bool(final_energy)), int(bool(check_inputs))
     p.timing_stride = int(timing_stride)
+    if tape is not None:
+        p.ckpt_every, p.tape, p.tape_bytes = int(ckpt_every), tape.data_ptr(), tape.numel()
     need = lib.pf_workspace_bytes(C.byref(grid), n_leaf, n_node, C.byref(p))
     if need == 0:
         # let the solver report the precise reason
@@ -217,7 +241,10 @@ def _solve(entry, D, S, n_leaf, n_node, *, graph=None, n_labels=None, c, tau, it
         workspace = torch.empty(need, dtype=torch.uint8, device=D.device)
     p.workspace, p.workspace_bytes = workspace.data_ptr(), workspace.numel()
     r = _Result()
-    u = labels = q = None
+    u = labels = q = ell = None
+    if return_ell:
+        ell = torch.empty((B, n_leaf, Z, Y, X), dtype=torch.float32, device=D.device)
+        r.ell = ell.data_ptr()
     if return_u:
         u = torch.empty((B, n_leaf, Z, Y, X), dtype=torch.float32, device=D.device)
         r.u = u.data_ptr()
@@ -242,7 +269,7 @@ def _solve(entry, D, S, n_leaf, n_node, *, graph=None, n_labels=None, c, tau, it
                    s_code, C.byref(p), C.byref(r), C.c_void_p(stream))
     if st != PF_OK:
         raise PseudoflowError(st, lib.pf_last_error().decode())
-    return SolveResult(u, labels, q, r.iters_done, r.energy, r.dual, r.gap,
+    return SolveResult(u, ell, labels, q, r.iters_done, r.energy, r.dual, r.gap,
                        r.max_simplex_err, r.max_flow_excess, r.kernel_ms, r.kernel_timed,
                        [hist[i] for i in range(r.gap_history_len)] if hist is not None else [],
                        workspace)
@@ -281,3 +308,124 @@ def solve_ishikawa(D, S, *, c: float, tau: float, iters: int, **kw) -> SolveResu
     n = int(D.shape[1])
     return _solve(library().solve_ishikawa, D, S, n, n - 1, n_labels=n, c=c, tau=tau,
                   iters=iters, **kw)
+
+
+# ------------------------------------------------------- differentiable ---
+
+def tape_bytes(shape, n_leaf: int, n_node: int, ndim: int, iters: int, ckpt_every: int) -> int:
+    B, Z, Y, X = shape
+    return int(library().pf_tape_bytes(C.byref(_Grid(B, ndim, Z, Y, X)), n_leaf, n_node,
+                                       iters, ckpt_every))
+
+
+class _Spec:
+    """Static arguments of a differentiable solve."""
+
+    def __init__(self, kind, graph, c, tau, iters, ckpt_every, s_mode, ndim):
+        self.kind, self.graph, self.c, self.tau = kind, graph, c, tau
+        self.iters, self.ckpt_every, self.s_mode, self.ndim = iters, ckpt_every, s_mode, ndim
+
+
+def _host_or_dev_S(S, s_mode):
+    if s_mode == "node_scalar":
+        return S.detach().float().cpu().numpy()
+    return S.detach().float().contiguous()
+
+
+class _PseudoflowFn:
+    """Holder of the torch.autograd.Function (built lazily: torch import)."""
+    cls = None
+
+
+def _autograd_fn():
+    if _PseudoflowFn.cls is not None:
+        return _PseudoflowFn.cls
+    torch = _torch()
+
+    class PseudoflowSolve(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, D, S, spec):
+            lib = library()
+            D = D.detach().float().contiguous()
+            grid = _grid_of(D, spec.ndim)
+            B, Z, Y, X = grid.batch, grid.nz, grid.ny, grid.nx
+            if spec.kind == "potts":
+                nl = nn = int(D.shape[1])
+            else:
+                nl, nn = _graph_sizes(spec.graph)
+            tb = lib.pf_tape_bytes(C.byref(grid), nl, nn, spec.iters, spec.ckpt_every)
+            tape = torch.empty(max(tb, 256), dtype=torch.uint8, device=D.device)
+            Sx = _host_or_dev_S(S, spec.s_mode)
+            kw = dict(c=spec.c, tau=spec.tau, iters=spec.iters, s_mode=spec.s_mode,
+                      ndim=spec.ndim, kernel="two_pass", final_energy=False, return_u=False,
+                      return_labels=False, return_ell=True, tape=tape,
+                      ckpt_every=spec.ckpt_every)
+            if spec.kind == "potts":
+                res = _solve(lib.solve_potts, D, Sx, nl, nn, n_labels=nl, **kw)
+            else:
+                res = _solve(lib.solve_dagmf, D, Sx, nl, nn, graph=spec.graph, **kw)
+            ctx.save_for_backward(D, S)
+            ctx.spec, ctx.tape, ctx.sizes = spec, tape, (nl, nn)
+            return res.ell
+
+        @staticmethod
+        def backward(ctx, grad_ell):
+            lib = library()
+            D, S = ctx.saved_tensors
+            spec, (nl, nn) = ctx.spec, ctx.sizes
+            grid = _grid_of(D, spec.ndim)
+            gl = grad_ell.detach().float().contiguous()
+            gD = torch.empty_like(D)
+            gS = torch.empty(S.shape, dtype=torch.float32, device=D.device)
+            ws_bytes = lib.pf_backward_workspace_bytes(C.byref(grid), nl, nn, spec.ckpt_every)
+            ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=D.device)
+            p = _Params()
+            p.iters, p.c, p.tau = spec.iters, float(spec.c), float(spec.tau)
+            p.storage, p.kernel = STORAGE["fp32"], KERNEL["two_pass"]
+            p.workspace, p.workspace_bytes = ws.data_ptr(), ws.numel()
+            p.ckpt_every, p.tape, p.tape_bytes = spec.ckpt_every, ctx.tape.data_ptr(), ctx.tape.numel()
+            keep: list = []
+            Sx = _host_or_dev_S(S, spec.s_mode)
+            s_ptr, s_code = _s_args(Sx, spec.s_mode, grid.batch, nn, grid.nz, grid.ny, grid.nx, keep)
+            stream = C.c_void_p(torch.cuda.current_stream(D.device).cuda_stream)
+            if spec.kind == "potts":
+                st = lib.solve_potts_backward(C.byref(grid), nl, C.c_void_p(D.data_ptr()),
+                                              C.c_void_p(s_ptr), s_code, C.byref(p),
+                                              C.c_void_p(gl.data_ptr()), C.c_void_p(gD.data_ptr()),
+                                              C.c_void_p(gS.data_ptr()), stream)
+            else:
+                gs = _graph_struct(spec.graph, keep)
+                st = lib.solve_dagmf_backward(C.byref(grid), C.byref(gs), C.c_void_p(D.data_ptr()),
+                                              C.c_void_p(s_ptr), s_code, C.byref(p),
+                                              C.c_void_p(gl.data_ptr()), C.c_void_p(gD.data_ptr()),
+                                              C.c_void_p(gS.data_ptr()), stream)
+            if st != PF_OK:
+                raise PseudoflowError(st, lib.pf_last_error().decode())
+            return gD, gS.to(S.dtype), None
+
+    _PseudoflowFn.cls = PseudoflowSolve
+    return PseudoflowSolve
+
+
+def potts_layer(D, S, *, c: float, tau: float, iters: int, ckpt_every: int = 10,
+                s_mode: Optional[str] = None, ndim: Optional[int] = None):
+    """Differentiable pseudo-flow Potts solve: returns the final log-labels
+    ell_K = ln u_K (float32, [B][n][Z][Y][X]); gradients flow to D and S.
+    S: device tensor [n] (per-label constants), [B][Z][Y][X] (shared field) or
+    [B][n][Z][Y][X] (per-label field)."""
+    if s_mode is None:
+        s_mode = {1: "node_scalar", 4: "shared_field", 5: "node_field"}[S.dim()]
+    nd = ndim if ndim is not None else (3 if D.shape[2] > 1 else 2)
+    spec = _Spec("potts", None, c, tau, iters, max(1, min(ckpt_every, iters)), s_mode, nd)
+    return _autograd_fn().apply(D, S, spec)
+
+
+def dagmf_layer(D, S, graph, *, c: float, tau: float, iters: int, ckpt_every: int = 10,
+                s_mode: Optional[str] = None, ndim: Optional[int] = None):
+    """Differentiable pseudo-flow DAGMF (or HMF) solve on ``graph``; as
+    ``potts_layer`` with one S value or field per non-source node."""
+    if s_mode is None:
+        s_mode = {1: "node_scalar", 4: "shared_field", 5: "node_field"}[S.dim()]
+    nd = ndim if ndim is not None else (3 if D.shape[2] > 1 else 2)
+    spec = _Spec("dagmf", graph, c, tau, iters, max(1, min(ckpt_every, iters)), s_mode, nd)
+    return _autograd_fn().apply(D, S, spec)

@@ -239,10 +239,42 @@ struct Timer {
     }
 };
 
+// Tape geometry: one float32 state (ell, then q) per checkpoint.
+struct TapeGeom {
+    size_t ell_bytes, slot_bytes;
+    int slots;
+};
+
+TapeGeom tape_geom(const pf_grid &g, int nl, int nn, int iters, int every) {
+    TapeGeom t{};
+    const size_t V = (size_t)g.nx * g.ny * g.nz;
+    t.ell_bytes = align256((size_t)g.batch * nl * V * 4);
+    t.slot_bytes = t.ell_bytes + align256((size_t)g.batch * nn * g.ndim * V * 4);
+    t.slots = every > 0 ? (iters + every - 1) / every : 0;
+    return t;
+}
+
+int check_tape(const Prob &p, const pf_params *P) {
+    if (!P->tape) return PF_OK;
+    if (P->storage != PF_FP32) return fail(PF_EUNSUPPORTED, "a recorded (differentiable) solve needs fp32 state");
+    if (P->ckpt_every < 1) return fail(PF_EINVAL, "ckpt_every must be >= 1");
+    if (P->gap_tol != 0.0 || P->warm_start)
+        return fail(PF_EINVAL, "a recorded solve runs a fixed iteration budget from the initial state");
+    if (!aligned(P->tape, 256)) return fail(PF_EINVAL, "tape is not 256-byte aligned");
+    const TapeGeom t = tape_geom(p.g, p.nl, p.nn, P->iters, P->ckpt_every);
+    if (P->tape_bytes < (size_t)t.slots * t.slot_bytes)
+        return fail(PF_ENOMEM, "tape of %zu bytes < %zu needed", P->tape_bytes, (size_t)t.slots * t.slot_bytes);
+    return PF_OK;
+}
+
 int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
-    const bool want_fused = P->kernel == PF_KERNEL_FUSED ||
+    int tst = check_tape(p, P);
+    if (tst != PF_OK) return tst;
+    if (P->tape && P->kernel == PF_KERNEL_FUSED)
+        return fail(PF_EUNSUPPORTED, "a recorded solve uses the two-pass kernels");
+    const bool want_fused = !P->tape && (P->kernel == PF_KERNEL_FUSED ||
                             (P->kernel == PF_KERNEL_AUTO &&
-                             fused_supported(p.g.ndim, p.nl, p.nn, p.ident));
+                             fused_preferred(p.g.ndim, p.nl, p.nn, p.ident, P->storage)));
     if (P->kernel == PF_KERNEL_FUSED && !fused_supported(p.g.ndim, p.nl, p.nn, p.ident))
         return fail(PF_EUNSUPPORTED, "fused kernel unavailable for this problem");
     const Layout lay = make_layout(p.g, p.nl, p.nn, P->storage, want_fused);
@@ -250,7 +282,7 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
         return fail(PF_ENOMEM, "workspace of %zu bytes < %zu needed", P->workspace_bytes, lay.total);
     if (!R) return fail(PF_EINVAL, "result is NULL");
     if ((R->u && !aligned(R->u, 4)) || (R->labels && !aligned(R->labels, 4)) ||
-        (R->q && !aligned(R->q, 4)))
+        (R->q && !aligned(R->q, 4)) || (R->ell && !aligned(R->ell, 4)))
         return fail(PF_EINVAL, "output pointers must be 4-byte aligned");
     if (R->gap_history && R->gap_history_cap < 0) return fail(PF_EINVAL, "gap_history_cap < 0");
 
@@ -334,7 +366,17 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
 
     Timer timer;
     int cur = 0;
+    const TapeGeom tg = tape_geom(p.g, p.nl, p.nn, P->iters, P->ckpt_every);
+    const size_t n_ell = (size_t)a.B * a.nl * a.V, n_q = (size_t)a.B * a.nn * nd * a.V;
     for (int it = 0; it < P->iters; ++it) {
+        if (P->tape && it % P->ckpt_every == 0) {
+            char *slot = static_cast<char *>(P->tape) + (size_t)(it / P->ckpt_every) * tg.slot_bytes;
+            if ((e = launch_copy_f(static_cast<const float *>(ell[0]), reinterpret_cast<float *>(slot),
+                                   n_ell, stream)) != hipSuccess ||
+                (e = launch_copy_f(static_cast<const float *>(q[0]),
+                                   reinterpret_cast<float *>(slot + tg.ell_bytes), n_q, stream)) != hipSuccess)
+                return hip_fail(e, "checkpoint");
+        }
         const bool timed = P->timing_stride > 0 && it % P->timing_stride == 0;
         if (timed) {
             hipEvent_t e0, e1;
@@ -403,6 +445,10 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
         if ((e = launch_export(a, nd, P->storage, R->u, R->labels, R->q, stream)) != hipSuccess)
             return hip_fail(e, "export");
     }
+    if (R->ell) {
+        if ((e = launch_export_ell(a, P->storage, R->ell, stream)) != hipSuccess)
+            return hip_fail(e, "export ell");
+    }
     if (!timer.ev.empty()) {
         if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "timing sync");
         double ms = 0.0;
@@ -415,6 +461,135 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
         R->kernel_ms = ms;
         R->kernel_timed = (int)(timer.ev.size() / 2);
     }
+    g_err.clear();
+    return PF_OK;
+}
+
+// Workspace of a backward call: results/flags/constants, then ckpt_every + 1
+// float32 segment states, pbar, lbar and the per-voxel capacity gradients.
+struct BwdLayout {
+    size_t consts, slots, pbar, lbar, sbar, total;
+    TapeGeom tg;
+};
+
+BwdLayout bwd_layout(const pf_grid &g, int nl, int nn, int every) {
+    BwdLayout L{};
+    const size_t V = (size_t)g.nx * g.ny * g.nz;
+    L.tg = tape_geom(g, nl, nn, every, every);
+    size_t off = 512;
+    L.consts = off;
+    off = align256(off + sizeof(ConstBlock));
+    L.slots = off;
+    off += (size_t)(every + 1) * L.tg.slot_bytes;
+    L.pbar = off;
+    off = align256(off + (size_t)g.batch * nn * g.ndim * V * 4);
+    L.lbar = off;
+    off = align256(off + (size_t)g.batch * nl * V * 4);
+    L.sbar = off;
+    off = align256(off + (size_t)g.batch * nn * V * 4);
+    L.total = off;
+    return L;
+}
+
+int run_backward(Prob &p, const pf_params *P, const float *grad_ell, float *grad_D, float *grad_S,
+                 hipStream_t stream) {
+    if (!P->tape) return fail(PF_EINVAL, "backward needs the tape of a recorded solve");
+    if (P->storage != PF_FP32) return fail(PF_EUNSUPPORTED, "backward needs fp32 state");
+    if (P->ckpt_every < 1) return fail(PF_EINVAL, "ckpt_every must be >= 1");
+    const TapeGeom tg = tape_geom(p.g, p.nl, p.nn, P->iters, P->ckpt_every);
+    if (!aligned(P->tape, 256) || P->tape_bytes < (size_t)tg.slots * tg.slot_bytes)
+        return fail(PF_ENOMEM, "tape smaller than pf_tape_bytes");
+    const BwdLayout L = bwd_layout(p.g, p.nl, p.nn, P->ckpt_every);
+    if (P->workspace_bytes < L.total)
+        return fail(PF_ENOMEM, "backward workspace of %zu bytes < %zu needed", P->workspace_bytes, L.total);
+    if (!grad_ell || !grad_D || !grad_S) return fail(PF_EINVAL, "gradient pointers must be set");
+    if (!aligned(grad_ell, 4) || !aligned(grad_D, 4) || !aligned(grad_S, 4))
+        return fail(PF_EINVAL, "gradient pointers must be 4-byte aligned");
+    const int nd = p.g.ndim;
+    char *ws = static_cast<char *>(P->workspace);
+    float *consts = reinterpret_cast<float *>(ws + L.consts);
+    const size_t V = (size_t)p.g.nx * p.g.ny * p.g.nz;
+    const size_t n_ell = (size_t)p.g.batch * p.nl * V, n_q = (size_t)p.g.batch * p.nn * nd * V;
+    auto slot_ell = [&](int j) { return reinterpret_cast<float *>(ws + L.slots + (size_t)j * L.tg.slot_bytes); };
+    auto slot_q = [&](int j) {
+        return reinterpret_cast<float *>(ws + L.slots + (size_t)j * L.tg.slot_bytes + L.tg.ell_bytes);
+    };
+    float *pbar = reinterpret_cast<float *>(ws + L.pbar);
+    float *lbar = reinterpret_cast<float *>(ws + L.lbar);
+    float *sbar = reinterpret_cast<float *>(ws + L.sbar);
+
+    StepArgs a{};
+    a.nx = p.g.nx;
+    a.ny = p.g.ny;
+    a.nz = p.g.nz;
+    a.V = (int32_t)V;
+    a.B = p.g.batch;
+    a.nl = p.nl;
+    a.nn = p.nn;
+    a.inv_c = 1.0f / P->c;
+    a.ctau = P->c * P->tau;
+    a.s_mode = p.s_mode;
+    a.D = p.D;
+    a.S = p.S;
+    a.W = consts + PF_MAX_NODES;
+    if (p.s_mode == PF_S_NODE_SCALAR) {
+        a.Sp = consts;
+        a.s_sb = 0, a.s_sa = 1, a.s_sv = 0;
+    } else if (p.s_mode == PF_S_SHARED_FIELD) {
+        a.Sp = p.S;
+        a.s_sb = a.V, a.s_sa = 0, a.s_sv = 1;
+    } else {
+        a.Sp = p.S;
+        a.s_sb = (int64_t)p.nn * a.V, a.s_sa = a.V, a.s_sv = 1;
+    }
+    hipError_t e;
+    {
+        ConstBlock cb{};
+        std::memcpy(cb.s_node, p.s_node, sizeof cb.s_node);
+        for (int A = 0; A < PF_MAX_NODES; ++A)
+            for (int Lf = 0; Lf < PF_MAX_LEAVES; ++Lf) cb.w[A * PF_MAX_LEAVES + Lf] = p.w.w[A][Lf];
+        if ((e = launch_upload(cb, consts, stream)) != hipSuccess) return hip_fail(e, "upload");
+    }
+    if ((e = launch_fill(grad_D, n_ell, 0.f, stream)) != hipSuccess ||
+        (e = launch_fill(pbar, n_q, 0.f, stream)) != hipSuccess ||
+        (e = launch_fill(sbar, (size_t)p.g.batch * p.nn * V, 0.f, stream)) != hipSuccess ||
+        (e = launch_copy_f(grad_ell, lbar, n_ell, stream)) != hipSuccess)
+        return hip_fail(e, "backward init");
+    const bool ident = p.ident;
+    const int K = P->iters, k = P->ckpt_every;
+    for (int seg = tg.slots - 1; seg >= 0; --seg) {
+        const int k0 = seg * k, k1 = std::min(K, k0 + k), m = k1 - k0;
+        const char *src = static_cast<const char *>(P->tape) + (size_t)seg * tg.slot_bytes;
+        if ((e = launch_copy_f(reinterpret_cast<const float *>(src), slot_ell(0), n_ell, stream)) != hipSuccess ||
+            (e = launch_copy_f(reinterpret_cast<const float *>(src + tg.ell_bytes), slot_q(0), n_q, stream)) !=
+                hipSuccess)
+            return hip_fail(e, "segment restore");
+        for (int j = 0; j < m; ++j) {   // recompute the segment's states, out of place
+            StepArgs f = a;
+            f.ell_in = slot_ell(j);
+            f.q_in = slot_q(j);
+            f.ell_out = slot_ell(j + 1);
+            if ((e = launch_label(f, ident, nd, PF_FP32, stream)) != hipSuccess) return hip_fail(e, "recompute");
+            f.ell_in = slot_ell(j + 1);
+            f.q_out = slot_q(j + 1);
+            if ((e = launch_flow(f, ident, nd, PF_FP32, stream)) != hipSuccess) return hip_fail(e, "recompute");
+        }
+        for (int step = k1 - 1; step >= k0; --step) {
+            const int j = step - k0;
+            AdjArgs g{};
+            g.q_k = slot_q(j);
+            g.ell_next = slot_ell(j + 1);
+            g.lbar = lbar;
+            g.pbar = pbar;
+            g.sbar = sbar;
+            g.dbar = grad_D;
+            g.first = step == K - 1;
+            if ((e = launch_adj_flow(a, g, ident, nd, stream)) != hipSuccess) return hip_fail(e, "adjoint flow");
+            if ((e = launch_adj_label(a, g, ident, nd, stream)) != hipSuccess) return hip_fail(e, "adjoint label");
+        }
+    }
+    if ((e = launch_reduce_sbar(sbar, p.g.batch, p.nn, V, p.s_mode, grad_S, stream)) != hipSuccess)
+        return hip_fail(e, "capacity gradient");
     g_err.clear();
     return PF_OK;
 }
@@ -435,8 +610,8 @@ size_t pf_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t n_node,
     // the same sizes serve the identity (Potts) and weighted families
     const bool fused = params->kernel == PF_KERNEL_FUSED ||
                        (params->kernel == PF_KERNEL_AUTO &&
-                        (fused_supported(grid->ndim, n_leaf, n_node, true) ||
-                         fused_supported(grid->ndim, n_leaf, n_node, false)));
+                        (fused_preferred(grid->ndim, n_leaf, n_node, true, params->storage) ||
+                         fused_preferred(grid->ndim, n_leaf, n_node, false, params->storage)));
     return make_layout(*grid, n_leaf, n_node, params->storage, fused).total;
 }
 
@@ -476,6 +651,50 @@ int solve_dagmf(const pf_grid *grid, const pf_graph *graph, const float *D, cons
 int solve_hmf(const pf_grid *grid, const pf_graph *graph, const float *D, const float *S,
               int32_t s_mode, const pf_params *params, pf_result *result, void *stream) {
     return solve_graph(grid, graph, true, D, S, s_mode, params, result, stream);
+}
+
+size_t pf_tape_bytes(const pf_grid *grid, int32_t n_leaf, int32_t n_node, int32_t iters,
+                     int32_t ckpt_every) {
+    if (check_grid(grid) != PF_OK || iters < 0 || ckpt_every < 1) return 0;
+    if (n_leaf < 1 || n_leaf > PF_MAX_LEAVES || n_node < 1 || n_node > PF_MAX_NODES) return 0;
+    const TapeGeom t = tape_geom(*grid, n_leaf, n_node, iters, ckpt_every);
+    return (size_t)t.slots * t.slot_bytes;
+}
+
+size_t pf_backward_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t n_node,
+                                   int32_t ckpt_every) {
+    if (check_grid(grid) != PF_OK || ckpt_every < 1) return 0;
+    if (n_leaf < 1 || n_leaf > PF_MAX_LEAVES || n_node < 1 || n_node > PF_MAX_NODES) return 0;
+    return bwd_layout(*grid, n_leaf, n_node, ckpt_every).total;
+}
+
+int solve_potts_backward(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
+                         int32_t s_mode, const pf_params *params, const float *grad_ell,
+                         float *grad_D, float *grad_S, void *stream) {
+    int st;
+    if ((st = check_grid(grid)) != PF_OK) return st;
+    if ((st = check_params(params)) != PF_OK) return st;
+    if (n_labels < 1) return fail(PF_EINVAL, "n_labels must be >= 1");
+    if (n_labels > PF_MAX_LEAVES) return fail(PF_EUNSUPPORTED, "n_labels > %d", PF_MAX_LEAVES);
+    Prob p;
+    p.g = *grid;
+    p.nl = p.nn = n_labels;
+    p.ident = true;
+    if ((st = check_inputs_common(p, D, S, s_mode)) != PF_OK) return st;
+    return run_backward(p, params, grad_ell, grad_D, grad_S, static_cast<hipStream_t>(stream));
+}
+
+int solve_dagmf_backward(const pf_grid *grid, const pf_graph *graph, const float *D,
+                         const float *S, int32_t s_mode, const pf_params *params,
+                         const float *grad_ell, float *grad_D, float *grad_S, void *stream) {
+    int st;
+    if ((st = check_grid(grid)) != PF_OK) return st;
+    if ((st = check_params(params)) != PF_OK) return st;
+    Prob p;
+    p.g = *grid;
+    if ((st = build_graph(graph, false, p)) != PF_OK) return st;
+    if ((st = check_inputs_common(p, D, S, s_mode)) != PF_OK) return st;
+    return run_backward(p, params, grad_ell, grad_D, grad_S, static_cast<hipStream_t>(stream));
 }
 
 int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,

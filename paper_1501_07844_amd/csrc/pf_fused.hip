@@ -249,6 +249,14 @@ bool fused_supported(int nd, int nl, int nn, bool identity) {
     return nl <= 16 && nn <= 16;
 }
 
+// PF_KERNEL_AUTO: the fused single pass where it measured faster than the
+// two-pass kernels on MI355X (3-D Potts with float32 state); the two-pass
+// kernels elsewhere (their lower register pressure wins for 16-bit state and
+// for label graphs).
+bool fused_preferred(int nd, int nl, int nn, bool identity, int storage) {
+    return identity && nd == 3 && storage == PF_FP32 && fused_supported(nd, nl, nn, identity);
+}
+
 FusedGeom fused_geometry(const StepArgs &a) {
     FusedGeom g{};
     g.tiles_x = (a.nx + FTX - 1) / FTX;

@@ -63,6 +63,17 @@ struct Layout {
     size_t total;
 };
 
+// Buffers of one reverse step (float32).
+struct AdjArgs {
+    const float *q_k;        // flows entering step k [B][nn][nd][V]
+    const float *ell_next;   // log-labels after step k [B][nl][V]
+    float *lbar;             // [B][nl][V], in/out
+    float *pbar;             // [B][nn][nd][V], in/out
+    float *sbar;             // [B][nn][V], accumulated
+    float *dbar;             // [B][nl][V], accumulated (the caller's dD)
+    int32_t first;           // last forward step: no later flow gradient
+};
+
 // Launch geometry of the fused kernel: (x, y) tiles times z chunks times problems.
 struct FusedGeom {
     int32_t tiles_x, tiles_y, n_chunks, cz;
@@ -82,6 +93,7 @@ hipError_t launch_label(const StepArgs &a, bool ident, int nd, int storage, hipS
 hipError_t launch_flow(const StepArgs &a, bool ident, int nd, int storage, hipStream_t s);
 hipError_t launch_fused(const StepArgs &a, bool ident, int nd, int storage, hipStream_t s);
 bool fused_supported(int nd, int nl, int nn, bool identity);
+bool fused_preferred(int nd, int nl, int nn, bool identity, int storage);
 FusedGeom fused_geometry(const StepArgs &a);
 hipError_t launch_copy_state(const StepArgs &a, int nd, int storage, hipStream_t s);
 hipError_t launch_energy(const StepArgs &a, bool ident, int nd, int storage,
@@ -89,5 +101,12 @@ hipError_t launch_energy(const StepArgs &a, bool ident, int nd, int storage,
 hipError_t launch_export(const StepArgs &a, int nd, int storage, float *u, int32_t *labels,
                          float *q, hipStream_t s);
 hipError_t launch_check(const StepArgs &a, int32_t *flag, hipStream_t s);
+hipError_t launch_export_ell(const StepArgs &a, int storage, float *ell, hipStream_t s);
+hipError_t launch_adj_flow(const StepArgs &a, const AdjArgs &g, bool ident, int nd, hipStream_t s);
+hipError_t launch_adj_label(const StepArgs &a, const AdjArgs &g, bool ident, int nd, hipStream_t s);
+hipError_t launch_fill(float *p, size_t n, float val, hipStream_t s);
+hipError_t launch_copy_f(const float *a, float *b, size_t n, hipStream_t s);
+hipError_t launch_reduce_sbar(const float *sbar, int B, int nn, size_t V, int s_mode, float *out,
+                              hipStream_t s);
 
 }  // namespace pf

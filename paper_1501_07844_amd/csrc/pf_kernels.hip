@@ -180,6 +180,12 @@ __global__ __launch_bounds__(kBlock) void k_export(StepArgs a, float *u, int32_t
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_export_ell(const T *ell, float *out, size_t n) {
+    const size_t stride = (size_t)gridDim.x * kBlock;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) out[i] = ld(ell, i);
+}
+
 __global__ __launch_bounds__(kBlock) void k_check(const float *D, size_t nD, const float *S,
                                                   size_t nS, int32_t *flag) {
     const size_t stride = (size_t)gridDim.x * kBlock;
@@ -368,6 +374,7 @@ hipError_t by_bucket(bool ident, int nl, int nn, F &f) {
     }
     if (nl <= 4 && nn <= 8) return f.template operator()<ND, 4, 8, false, T>();
     if (nl <= 8 && nn <= 16) return f.template operator()<ND, 8, 16, false, T>();
+    if (nn <= 16) return f.template operator()<ND, 16, 16, false, T>();
     return f.template operator()<ND, 16, 32, false, T>();
 }
 
@@ -467,6 +474,14 @@ hipError_t launch_export(const StepArgs &a, int nd, int storage, float *u, int32
             k_export<2, T><<<voxel_grid(a), kBlock, 0, s>>>(a, u, labels, q);
         else
             k_export<3, T><<<voxel_grid(a), kBlock, 0, s>>>(a, u, labels, q);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_export_ell(const StepArgs &a, int storage, float *ell, hipStream_t s) {
+    const size_t n = (size_t)a.B * a.nl * a.V;
+    return dispatch_type(storage, [&]<typename T>() {
+        k_export_ell<T><<<stride_blocks(n), kBlock, 0, s>>>(static_cast<const T *>(a.ell_in), ell, n);
         return hipGetLastError();
     });
 }

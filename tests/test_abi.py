@@ -43,7 +43,7 @@ def test_every_declared_symbol_is_exported():
     lib = pf.library()
     for name in _declared():
         assert hasattr(lib, name), name
-    assert lib.pf_abi_version() == 1
+    assert lib.pf_abi_version() == pf.ABI_VERSION == 2
 
 
 def _grid(B=1, nd=3, Z=8, Y=9, X=10):
@@ -225,3 +225,72 @@ def test_binding_refuses_cpu_tensors():
     D = torch.zeros(1, 3, 1, 4, 4)
     with pytest.raises(ValueError):
         pf.solve_potts(D, 0.5, c=1.0, tau=0.1, iters=1)
+
+
+def test_tape_and_backward_workspace_accounting():
+    """One float32 state (labels, then flows, each 256-byte aligned) per
+    checkpoint, ceil(K / k) checkpoints; the backward workspace holds k + 1
+    segment states plus the adjoint flow, label and capacity fields."""
+    lib = pf.library()
+    g = _grid(2, 3, 8, 9, 10)
+    V = 8 * 9 * 10
+    al = lambda n: (n + 255) // 256 * 256
+    slot = al(2 * 4 * V * 4) + al(2 * 6 * 3 * V * 4)
+    for K, k in ((10, 5), (11, 5), (1, 1), (7, 10), (0, 3)):
+        assert lib.pf_tape_bytes(C.byref(g), 4, 6, K, k) == -(-K // k) * slot
+    for k in (1, 4, 10):
+        n = lib.pf_backward_workspace_bytes(C.byref(g), 4, 6, k)
+        adj = al(2 * 6 * 3 * V * 4) + al(2 * 4 * V * 4) + al(2 * 6 * V * 4)
+        assert (k + 1) * slot + adj <= n <= (k + 1) * slot + adj + 64 * 1024
+    assert lib.pf_tape_bytes(C.byref(g), 4, 6, 10, 0) == 0
+    assert lib.pf_tape_bytes(C.byref(g), 4, 6, -1, 2) == 0
+    assert lib.pf_tape_bytes(C.byref(g), 17, 6, 10, 2) == 0
+    assert lib.pf_backward_workspace_bytes(C.byref(g), 4, 6, 0) == 0
+
+
+@pytest.mark.parametrize("case,code", [
+    ("no_tape", pf.PF_EINVAL), ("bf16", pf.PF_EUNSUPPORTED), ("ckpt0", pf.PF_EINVAL),
+    ("small_tape", pf.PF_ENOMEM), ("misaligned_tape", pf.PF_ENOMEM),
+    ("small_ws", pf.PF_ENOMEM), ("null_grad", pf.PF_EINVAL), ("misaligned_grad", pf.PF_EINVAL),
+    ("bad_params", pf.PF_EINVAL),
+])
+def test_backward_argument_errors(case, code):
+    lib = pf.library()
+    g = _grid()
+    tb = lib.pf_tape_bytes(C.byref(g), 3, 3, 5, 2)
+    p = _params(ckpt_every=2, tape=512 * 1024, tape_bytes=tb)
+    p.workspace_bytes = lib.pf_backward_workspace_bytes(C.byref(g), 3, 3, 2)
+    gl, gd, gs = DEV, DEV + 4096, DEV + 8192
+    if case == "no_tape":
+        p.tape = None
+    elif case == "bf16":
+        p.storage = 1
+    elif case == "ckpt0":
+        p.ckpt_every = 0
+    elif case == "small_tape":
+        p.tape_bytes = tb - 1
+    elif case == "misaligned_tape":
+        p.tape = 512 * 1024 + 4
+    elif case == "small_ws":
+        p.workspace_bytes -= 256
+    elif case == "null_grad":
+        gd = 0
+    elif case == "misaligned_grad":
+        gs += 2
+    elif case == "bad_params":
+        p.c = 0.0
+    st = lib.solve_potts_backward(C.byref(g), 3, C.c_void_p(DEV), C.c_void_p(SADDR), 0,
+                                  C.byref(p), C.c_void_p(gl), C.c_void_p(gd), C.c_void_p(gs), None)
+    assert st == code, (case, lib.pf_last_error())
+
+
+def test_dag_backward_rejects_bad_graph():
+    lib = pf.library()
+    g = _grid()
+    par = (C.c_int32 * 2)(0, 1)
+    chi = (C.c_int32 * 2)(1, 0)            # cycle
+    gr = pf._Graph(2, 2, par, chi, None)
+    p = _params(ckpt_every=1, tape=512 * 1024, tape_bytes=1 << 30)
+    st = lib.solve_dagmf_backward(C.byref(g), C.byref(gr), C.c_void_p(DEV), C.c_void_p(SADDR), 0,
+                                  C.byref(p), C.c_void_p(DEV), C.c_void_p(DEV), C.c_void_p(DEV), None)
+    assert st == pf.PF_EGRAPH

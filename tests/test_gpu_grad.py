@@ -1,0 +1,194 @@
+"""GPU parity of the differentiable solve (recorded forward + reverse
+kernels through the C ABI) against autograd through the float64 oracle.
+
+Tolerance: float32 state and arithmetic against the float64 reference, so a
+gradient is compared as max |g_gpu - g_ref| <= G_RTOL * max |g_ref| over the
+whole tensor.  Each unrolled step is a contraction-like map of the float32
+rounding (about 1e-7 relative per step); the reverse pass accumulates D and S
+gradients over K steps, so K = 100 allows a few 1e-6 relative, and 2e-4
+(small cases) / 1e-3 (the full 100-iteration batch) leave a wide margin while
+any wrong term (a dropped adjoint path, a wrong sign or a missing mask) shows
+up at order one.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1501_07844_amd as pf
+from paper_1501_07844_amd import synth
+from oracle import pseudoflow_oracle as O
+
+pytestmark = pytest.mark.gpu
+G_RTOL = 2e-4
+F64 = torch.float64
+
+
+def _graph(g):
+    return O.OracleGraph(g.n_nodes, g.parent, g.child, g.weight)
+
+
+def _oracle_grad(p, iters, weights, D=None, S=None):
+    D = torch.tensor(p.D if D is None else D, dtype=F64, requires_grad=True)
+    S = torch.tensor(np.asarray(p.S if S is None else S), dtype=F64, requires_grad=True)
+    if p.kind == "potts":
+        ell = O.solve_potts(D, S, p.s_mode, p.c, p.tau, iters, p.ndim, history=False)["ell"]
+    else:
+        ell = O.solve_dagmf(D, S, p.s_mode, _graph(p.graph), p.c, p.tau, iters, p.ndim,
+                            history=False)["ell"]
+    (ell * torch.as_tensor(weights, dtype=F64)).sum().backward()
+    return ell.detach().numpy(), D.grad.numpy(), S.grad.numpy()
+
+
+def _gpu_grad(p, iters, ckpt, weights):
+    D = torch.from_numpy(np.ascontiguousarray(p.D)).cuda().requires_grad_(True)
+    S = torch.from_numpy(np.ascontiguousarray(np.asarray(p.S, np.float32))).cuda().requires_grad_(True)
+    kw = dict(c=p.c, tau=p.tau, iters=iters, ckpt_every=ckpt, s_mode=p.s_mode, ndim=p.ndim)
+    if p.kind == "potts":
+        ell = pf.potts_layer(D, S, **kw)
+    else:
+        ell = pf.dagmf_layer(D, S, p.graph, **kw)
+    (ell * torch.as_tensor(weights, device="cuda")).sum().backward()
+    torch.cuda.synchronize()
+    return ell.detach().cpu().numpy(), D.grad.cpu().numpy(), S.grad.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max()) / max(float(np.abs(b).max()), 1e-30)
+
+
+def _cases():
+    rng = np.random.default_rng(7)
+    dag = synth.random_dag(rng, 3, 5)
+    tree = synth.random_tree(rng, 2, 4)
+    deep = synth.random_dag(rng, 9, 12)
+    return {
+        "potts2d_shared_B2": (synth.random_potts(11, (1, 37, 70), 2, 4, batch=2, s_mode="shared_field",
+                                                 c=2.0, tau=0.125), 13, 5),
+        "potts3d_scalar": (synth.random_potts(12, (9, 17, 21), 3, 3, s_mode="node_scalar",
+                                              c=1.0, tau=0.125), 9, 4),
+        "potts2d_nodefield_nl5": (synth.random_potts(13, (1, 33, 65), 2, 5, s_mode="node_field",
+                                                     c=2.0, tau=0.125), 12, 3),
+        "potts3d_nl12": (synth.random_potts(17, (5, 9, 70), 3, 12, s_mode="shared_field",
+                                            c=2.0, tau=0.125), 6, 6),
+        "dag2d_nodefield_B2": (synth.random_problem(14, (1, 26, 37), 2, dag, batch=2,
+                                                    s_mode="node_field", c=4.0, tau=0.0625), 8, 3),
+        "tree3d_scalar": (synth.random_problem(15, (6, 8, 33), 3, tree, s_mode="node_scalar",
+                                               c=4.0, tau=0.0625, kind="hmf"), 7, 3),
+        "dag3d_shared": (synth.random_problem(16, (5, 9, 40), 3, dag, s_mode="shared_field",
+                                              c=4.0, tau=0.0625), 5, 2),
+        "deep_dag3d_scalar": (synth.random_problem(18, (4, 6, 67), 3, deep, s_mode="node_scalar",
+                                                   c=8.0, tau=1 / 12), 6, 4),
+    }
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_gradient_matches_oracle(name):
+    p, iters, ckpt = CASES[name]
+    w = np.random.default_rng(1).standard_normal(p.D.shape).astype(np.float32)
+    ell_r, gD_r, gS_r = _oracle_grad(p, iters, w)
+    ell_g, gD_g, gS_g = _gpu_grad(p, iters, ckpt, w)
+    de, eD, eS = float(np.abs(ell_g - ell_r).max()), _rel(gD_g, gD_r), _rel(gS_g, gS_r)
+    print(f"{name}: max|dell|={de:.2e} rel dD={eD:.2e} rel dS={eS:.2e}", flush=True)
+    assert de <= 1e-4
+    assert eD <= G_RTOL and eS <= G_RTOL
+
+
+@pytest.mark.parametrize("name", ["potts2d_shared_B2", "dag2d_nodefield_B2"])
+def test_checkpoint_interval_does_not_change_gradients(name):
+    """Recomputed segments reproduce the forward states bit for bit, so the
+    checkpoint interval (1, 3, all iterations) changes nothing."""
+    p, iters, _ = CASES[name]
+    w = np.random.default_rng(2).standard_normal(p.D.shape).astype(np.float32)
+    ref = _gpu_grad(p, iters, iters, w)
+    for k in (1, 3):
+        got = _gpu_grad(p, iters, k, w)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), k
+
+
+def test_layer_forward_equals_plain_solve():
+    p, iters, _ = CASES["potts3d_scalar"]
+    D = torch.from_numpy(p.D).cuda()
+    ell = pf.potts_layer(D, torch.tensor(p.S).cuda(), c=p.c, tau=p.tau, iters=iters,
+                         s_mode=p.s_mode)
+    res = pf.solve_potts(D, np.asarray(p.S), c=p.c, tau=p.tau, iters=iters, kernel="two_pass",
+                         s_mode=p.s_mode)
+    assert float((torch.exp(ell) - res.u).abs().max()) <= 1e-6
+
+
+@pytest.mark.parametrize("iters", [1, 9])
+def test_zero_capacity_closed_form(iters):
+    """S = 0: ell_K = log softmax(-K D / c) and d(sum w ell_K)/dD =
+    -(K / c)(w - u sum_L w_L), in float64 on the host from the same D."""
+    p = synth.random_potts(25, (3, 19, 40), 3, 6, s_mode="node_scalar", c=3.0, tau=0.125)
+    D = torch.from_numpy(p.D).cuda().requires_grad_(True)
+    S = torch.zeros(6, device="cuda", requires_grad=True)
+    w = torch.randn(D.shape, generator=torch.Generator().manual_seed(3))
+    ell = pf.potts_layer(D, S, c=p.c, tau=p.tau, iters=iters)
+    (ell * w.cuda()).sum().backward()
+    t = -iters * torch.tensor(p.D, dtype=F64) / p.c
+    u = torch.softmax(t, dim=1)
+    expect = -(iters / p.c) * (w.double() - u * w.double().sum(dim=1, keepdim=True))
+    assert float((ell.detach().cpu().double() - torch.log_softmax(t, dim=1)).abs().max()) <= 2e-5
+    assert float((D.grad.cpu().double() - expect).abs().max()) <= 1e-5 * float(expect.abs().max())
+
+
+def test_zero_iterations():
+    """K = 0: ell is the initial state and both gradients vanish."""
+    p = synth.random_potts(26, (1, 9, 12), 2, 3, s_mode="shared_field")
+    D = torch.from_numpy(p.D).cuda().requires_grad_(True)
+    S = torch.from_numpy(np.asarray(p.S)).cuda().requires_grad_(True)
+    ell = pf.potts_layer(D, S, c=p.c, tau=p.tau, iters=0)
+    ell.sum().backward()
+    assert torch.allclose(ell, torch.full_like(ell, -float(np.log(3))))
+    assert float(D.grad.abs().max()) == 0.0 and float(S.grad.abs().max()) == 0.0
+
+
+def test_recorded_solve_argument_errors():
+    p = synth.random_potts(27, (1, 8, 8), 2, 3, s_mode="node_scalar")
+    D = torch.from_numpy(p.D).cuda()
+    tape = torch.empty(pf.tape_bytes((1, 1, 8, 8), 3, 3, 2, 10, 5), dtype=torch.uint8, device="cuda")
+    base = dict(c=p.c, tau=p.tau, iters=10, s_mode="node_scalar", ndim=2, tape=tape, ckpt_every=5)
+    S = np.asarray(p.S)
+    cases = [({"storage": "bf16"}, pf.PF_EUNSUPPORTED), ({"kernel": "fused"}, pf.PF_EUNSUPPORTED),
+             ({"gap_every": 2, "gap_tol": 1e-3}, pf.PF_EINVAL), ({"ckpt_every": 0}, pf.PF_EINVAL),
+             ({"iters": 11}, pf.PF_ENOMEM)]
+    for extra, code in cases:
+        kw = dict(base)
+        kw.update(extra)
+        with pytest.raises(pf.PseudoflowError) as e:
+            pf.solve_potts(D, S, **kw)
+        assert e.value.code == code, (extra, e.value)
+    pf.solve_potts(D, S, **base)          # the valid call goes through
+
+
+def test_full_size_diff_batch_sampled():
+    """16 Potts problems of 256 x 256, 5 labels, 100 unrolled iterations,
+    checkpoint every 10, cross-entropy loss against the ground-truth labels
+    (mean over the whole batch).  Problems are independent, so the gradient
+    of problem 3 is compared with autograd through the oracle on that problem
+    alone; every other problem's gradient is checked finite and non-zero."""
+    p = synth.diff_batch()
+    B, nl = p.D.shape[:2]
+    gt = torch.from_numpy(p.gt.astype(np.int64)).cuda()          # [B][1][Y][X]
+    D = torch.from_numpy(p.D).cuda().requires_grad_(True)
+    S = torch.from_numpy(np.asarray(p.S)).cuda().requires_grad_(True)
+    ell = pf.potts_layer(D, S, c=p.c, tau=p.tau, iters=p.iters,
+                         ckpt_every=p.extra["checkpoint_every"])
+    loss = -torch.gather(ell, 1, gt.unsqueeze(1)).mean()
+    loss.backward()
+    torch.cuda.synchronize()
+    n_vox = float(gt.numel())
+    b = 3
+    w = np.zeros((1,) + p.D.shape[1:], np.float32)
+    np.put_along_axis(w, p.gt[b:b + 1, None].astype(np.int64), -1.0 / n_vox, axis=1)
+    _, gD_r, gS_r = _oracle_grad(p, p.iters, w, D=p.D[b:b + 1], S=np.asarray(p.S)[b:b + 1])
+    gD, gS = D.grad.cpu().numpy(), S.grad.cpu().numpy()
+    eD, eS = _rel(gD[b:b + 1], gD_r), _rel(gS[b:b + 1], gS_r)
+    print(f"diff batch problem {b}: rel dD={eD:.2e} rel dS={eS:.2e}", flush=True)
+    assert eD <= 1e-3 and eS <= 1e-3
+    assert np.isfinite(gD).all() and np.isfinite(gS).all()
+    assert all(np.abs(gD[i]).max() > 0 for i in range(B))
