@@ -321,9 +321,10 @@ def tape_bytes(shape, n_leaf: int, n_node: int, ndim: int, iters: int, ckpt_ever
 class _Spec:
     """Static arguments of a differentiable solve."""
 
-    def __init__(self, kind, graph, c, tau, iters, ckpt_every, s_mode, ndim):
+    def __init__(self, kind, graph, c, tau, iters, ckpt_every, s_mode, ndim, backward_kernel):
         self.kind, self.graph, self.c, self.tau = kind, graph, c, tau
         self.iters, self.ckpt_every, self.s_mode, self.ndim = iters, ckpt_every, s_mode, ndim
+        self.backward_kernel = KERNEL[backward_kernel]
 
 
 def _host_or_dev_S(S, s_mode):
@@ -381,7 +382,7 @@ def _autograd_fn():
             ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=D.device)
             p = _Params()
             p.iters, p.c, p.tau = spec.iters, float(spec.c), float(spec.tau)
-            p.storage, p.kernel = STORAGE["fp32"], KERNEL["two_pass"]
+            p.storage, p.kernel = STORAGE["fp32"], spec.backward_kernel
             p.workspace, p.workspace_bytes = ws.data_ptr(), ws.numel()
             p.ckpt_every, p.tape, p.tape_bytes = spec.ckpt_every, ctx.tape.data_ptr(), ctx.tape.numel()
             keep: list = []
@@ -408,24 +409,30 @@ def _autograd_fn():
 
 
 def potts_layer(D, S, *, c: float, tau: float, iters: int, ckpt_every: int = 10,
-                s_mode: Optional[str] = None, ndim: Optional[int] = None):
+                s_mode: Optional[str] = None, ndim: Optional[int] = None,
+                backward_kernel: str = "auto"):
     """Differentiable pseudo-flow Potts solve: returns the final log-labels
     ell_K = ln u_K (float32, [B][n][Z][Y][X]); gradients flow to D and S.
     S: device tensor [n] (per-label constants), [B][Z][Y][X] (shared field) or
-    [B][n][Z][Y][X] (per-label field)."""
+    [B][n][Z][Y][X] (per-label field).  The forward records a checkpoint
+    every ``ckpt_every`` iterations; ``backward_kernel`` picks the reverse
+    step ("fused", "two_pass" or "auto")."""
     if s_mode is None:
         s_mode = {1: "node_scalar", 4: "shared_field", 5: "node_field"}[S.dim()]
     nd = ndim if ndim is not None else (3 if D.shape[2] > 1 else 2)
-    spec = _Spec("potts", None, c, tau, iters, max(1, min(ckpt_every, iters)), s_mode, nd)
+    spec = _Spec("potts", None, c, tau, iters, max(1, min(ckpt_every, iters)), s_mode, nd,
+                 backward_kernel)
     return _autograd_fn().apply(D, S, spec)
 
 
 def dagmf_layer(D, S, graph, *, c: float, tau: float, iters: int, ckpt_every: int = 10,
-                s_mode: Optional[str] = None, ndim: Optional[int] = None):
+                s_mode: Optional[str] = None, ndim: Optional[int] = None,
+                backward_kernel: str = "auto"):
     """Differentiable pseudo-flow DAGMF (or HMF) solve on ``graph``; as
     ``potts_layer`` with one S value or field per non-source node."""
     if s_mode is None:
         s_mode = {1: "node_scalar", 4: "shared_field", 5: "node_field"}[S.dim()]
     nd = ndim if ndim is not None else (3 if D.shape[2] > 1 else 2)
-    spec = _Spec("dagmf", graph, c, tau, iters, max(1, min(ckpt_every, iters)), s_mode, nd)
+    spec = _Spec("dagmf", graph, c, tau, iters, max(1, min(ckpt_every, iters)), s_mode, nd,
+                 backward_kernel)
     return _autograd_fn().apply(D, S, spec)

@@ -13,9 +13,19 @@
 //       pbar^{(k)} = J_Proj(p)^T qbar_{k+1},  Sbar += (p . qbar) / |p| if |p| > S
 //   KB: Ubar = c tau div pbar^{(k)},  g = lbar + (W^T Ubar) * u'   (total dLoss/dell_{k+1})
 //       lbar <- g - u' sum_L g_L,  Dbar -= lbar / c
-// KA reads lbar at x and x + e_k, KB reads pbar at x and x - e_k, so each is
-// its own launch; both update their buffers in place (a thread writes only
-// its own voxel).
+// KA at x reads lbar at x and x + e_k; KB at x reads the new pbar at x and
+// x - e_k.  Two variants:
+//   * two kernels (KA, then KB), each updating its buffer in place (a thread
+//     writes only its own voxel);
+//   * one fused kernel: a block owns an RTX x RTY tile of (x, y) columns and
+//     marches a chunk of z planes; the new pbar of the plane is exchanged
+//     through LDS, the points one column / one row before the tile are
+//     recomputed by an extra halo wavefront, and along z the backward
+//     neighbour is the thread's own previous plane.  lbar and pbar are read
+//     from one buffer and written to another, since the halo points read
+//     values that the neighbouring blocks overwrite.
+// Both variants evaluate the same per-point expressions (ka_point, kb_point)
+// and give the same gradients bit for bit.
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -28,26 +38,31 @@ namespace {
 
 using namespace dev;
 
+constexpr int RTX = 64;               // tile width = one wavefront
+constexpr int RTY = 8;                // owned rows per tile (the fused forward tile)
+constexpr int RTHREADS = RTX * (RTY + 1);
+
+// KA at voxel c (index uv) of problem b: the new pbar (out, 0 on the last
+// index of each axis and for padding flows), the capacity-gradient
+// contributions (sb) and the new log-labels and incoming lbar at the voxel
+// (e0, l0, which KB needs).  All loads are issued first, unconditionally
+// (clamped indices stay in bounds).
 template <int ND, int NLMAX, int NNMAX, bool IDENT>
-__global__ __launch_bounds__(kBlock) void k_adj_flow(StepArgs a, AdjArgs g) {
-    const int v = blockIdx.x * kBlock + threadIdx.x;
-    if (v >= a.V) return;
-    const int b = blockIdx.y;
-    const Coord c = coord_of(v, a.nx, a.ny);
+__device__ __forceinline__ void ka_point(const StepArgs &a, const AdjArgs &g, int b,
+                                         const Coord &c, unsigned uv, float (&out)[NNMAX][ND],
+                                         float (&sb)[NNMAX], float (&e0)[NLMAX],
+                                         float (&l0)[NLMAX]) {
     const size_t V = (size_t)a.V;
-    const unsigned uv = (unsigned)v;
     const bool h[3] = {c.x < a.nx - 1, c.y < a.ny - 1, ND == 3 && c.z < a.nz - 1};
     const int off[3] = {h[0] ? 1 : 0, h[1] ? a.nx : 0, h[2] ? a.nx * a.ny : 0};
 
-    // loads: new labels (x and forward neighbours), lbar (same), old flows,
-    // pbar of the later step, capacities
-    float e0[NLMAX], en[NLMAX][ND], l0[NLMAX], lnb[NLMAX][ND];
+    float en[NLMAX][ND], lnb[NLMAX][ND];
     float qv[NNMAX][ND], pb[NNMAX][ND], sv[NNMAX];
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L) {
         const int Lc = L < a.nl ? L : a.nl - 1;
         const float *el = field<float>(g.ell_next, b, a.nl, Lc, V);
-        const float *lb = field<float>(g.lbar, b, a.nl, Lc, V);
+        const float *lb = field<float>(g.lbar_in, b, a.nl, Lc, V);
         e0[L] = ldf(el, uv);
         l0[L] = ldf(lb, uv);
 #pragma unroll
@@ -62,11 +77,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_flow(StepArgs a, AdjArgs g) {
 #pragma unroll
         for (int k = 0; k < ND; ++k) {
             qv[A][k] = ldf(field<float>(g.q_k, b, a.nn * ND, Ac * ND + k, V), uv);
-            pb[A][k] = ldf(field<float>(g.pbar, b, a.nn * ND, Ac * ND + k, V), uv);
+            pb[A][k] = ldf(field<float>(g.pbar_in, b, a.nn * ND, Ac * ND + k, V), uv);
         }
-        sv[A] = smooth(a, b, Ac, v);
+        sv[A] = smooth(a, b, Ac, (int)uv);
     }
-    // forward quantities: grad u', grad U, p
+    // forward quantities (grad u', grad U, p) and grad lbar
     float gu[NLMAX][ND], gl[NLMAX][ND];
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L) {
@@ -74,47 +89,134 @@ __global__ __launch_bounds__(kBlock) void k_adj_flow(StepArgs a, AdjArgs g) {
 #pragma unroll
         for (int k = 0; k < ND; ++k) {
             gu[L][k] = h[k] ? __expf(en[L][k]) - u0 : 0.f;
-            gl[L][k] = h[k] ? lnb[L][k] - l0[L] : 0.f;      // grad of lbar
+            gl[L][k] = h[k] ? lnb[L][k] - l0[L] : 0.f;
         }
     }
 #pragma unroll
     for (int A = 0; A < NNMAX; ++A) {
-        if (A < a.nn) {
-            float G[3], GL[3], p[ND], qb[ND];
-            grad_U<ND, NLMAX, IDENT>(a, A, gu, G);
-            grad_U<ND, NLMAX, IDENT>(a, A, gl, GL);       // grad (W lbar)
-            float n2 = 0.f, dot = 0.f;
+        float G[3], GL[3], p[ND], qb[ND];
+        grad_U<ND, NLMAX, IDENT>(a, A, gu, G);
+        grad_U<ND, NLMAX, IDENT>(a, A, gl, GL);       // grad (W lbar)
+        float n2 = 0.f, dot = 0.f;
 #pragma unroll
-            for (int k = 0; k < ND; ++k) {
-                p[k] = h[k] ? fmaf(-a.ctau, G[k], qv[A][k]) : 0.f;
-                qb[k] = g.first ? 0.f : (h[k] ? pb[A][k] + GL[k] * a.inv_c : 0.f);
-                n2 = fmaf(p[k], p[k], n2);
-                dot = fmaf(p[k], qb[k], dot);
-            }
-            const float S = sv[A];
-            float out[ND], sbar = 0.f;
-            if (n2 > S * S) {
-                const float rn = rsqrtf(n2);
-                const float sc = S * rn;
-                const float proj = dot / n2;
+        for (int k = 0; k < ND; ++k) {
+            p[k] = h[k] ? fmaf(-a.ctau, G[k], qv[A][k]) : 0.f;
+            qb[k] = g.first ? 0.f : (h[k] ? pb[A][k] + GL[k] * a.inv_c : 0.f);
+            n2 = fmaf(p[k], p[k], n2);
+            dot = fmaf(p[k], qb[k], dot);
+        }
+        const float S = sv[A];
+        float s = 0.f;
+        if (n2 > S * S) {
+            const float rn = rsqrtf(n2);
+            const float sc = S * rn;
+            const float proj = dot / n2;
 #pragma unroll
-                for (int k = 0; k < ND; ++k) out[k] = sc * (qb[k] - proj * p[k]);
-                sbar = dot * rn;
-            } else {
+            for (int k = 0; k < ND; ++k) out[A][k] = sc * (qb[k] - proj * p[k]);
+            s = dot * rn;
+        } else {
 #pragma unroll
-                for (int k = 0; k < ND; ++k) out[k] = qb[k];
-            }
+            for (int k = 0; k < ND; ++k) out[A][k] = qb[k];
+        }
+        const bool live = A < a.nn;
 #pragma unroll
-            for (int k = 0; k < ND; ++k) {
-                float *po = field_w<float>(g.pbar, b, a.nn * ND, A * ND + k, V);
-                *reinterpret_cast<float *>(reinterpret_cast<char *>(po) + uv * 4u) =
-                    h[k] ? out[k] : 0.f;
-            }
-            float *sb = field_w<float>(g.sbar, b, a.nn, A, V);
-            float *sp = reinterpret_cast<float *>(reinterpret_cast<char *>(sb) + uv * 4u);
-            *sp += sbar;
+        for (int k = 0; k < ND; ++k) out[A][k] = (live && h[k]) ? out[A][k] : 0.f;
+        sb[A] = live ? s : 0.f;
+    }
+}
+
+// KB at one voxel: e, lb = new log-labels and incoming lbar at the voxel,
+// p0 / pm = new pbar at x / at x - e_k.  Returns the new lbar (tb).
+template <int ND, int NLMAX, int NNMAX, bool IDENT>
+__device__ __forceinline__ void kb_point(const StepArgs &a, const float (&e)[NLMAX],
+                                         const float (&lb)[NLMAX], const float (&p0)[NNMAX][3],
+                                         const float (&pm)[NNMAX][3], const bool (&fwd)[3],
+                                         const bool (&bwd)[3], float (&tb)[NLMAX]) {
+    // ubar_L = sum_A W[A][L] * c tau div pbar_A
+    float ub[NLMAX];
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L) ub[L] = 0.f;
+#pragma unroll
+    for (int A = 0; A < NNMAX; ++A) {
+        const float dv = a.ctau * div_from<ND>(p0[A], pm[A], fwd, bwd);
+        if constexpr (IDENT) {
+            ub[A] += dv;
+        } else {
+#pragma unroll
+            for (int L = 0; L < NLMAX; ++L) ub[L] = fmaf(wgt(a, A, L), dv, ub[L]);
         }
     }
+    // adjoint of ell_{k+1} = t - LSE(t): tbar = gtot - u' sum(gtot)
+    float gt[NLMAX], u[NLMAX], sg = 0.f;
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L) {
+        u[L] = __expf(e[L]);
+        gt[L] = L < a.nl ? fmaf(ub[L], u[L], lb[L]) : 0.f;
+        sg += gt[L];
+    }
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L) tb[L] = gt[L] - u[L] * sg;
+}
+
+// Capacity gradient of one voxel: summed over the flows into one field when
+// every flow shares one capacity field, else one value per flow.
+template <int NNMAX>
+__device__ __forceinline__ void add_sbar(const StepArgs &a, const AdjArgs &g, int b, unsigned uv,
+                                         const float (&sb)[NNMAX]) {
+    const size_t V = (size_t)a.V;
+    if (g.sbar_shared) {
+        float s = 0.f;
+#pragma unroll
+        for (int A = 0; A < NNMAX; ++A) s += sb[A];
+        float *p = field_w<float>(g.sbar, b, 1, 0, V);
+        sto(p, uv, ldf(p, uv) + s);
+    } else {
+#pragma unroll
+        for (int A = 0; A < NNMAX; ++A) {
+            if (A < a.nn) {
+                float *p = field_w<float>(g.sbar, b, a.nn, A, V);
+                sto(p, uv, ldf(p, uv) + sb[A]);
+            }
+        }
+    }
+}
+
+// Stores of KB at an owned voxel: the new lbar, and D's gradient -= lbar / c.
+template <int NLMAX>
+__device__ __forceinline__ void store_label_adjoint(const StepArgs &a, const AdjArgs &g, int b,
+                                                    unsigned uv, const float (&tb)[NLMAX]) {
+    const size_t V = (size_t)a.V;
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L) {
+        if (L < a.nl) {
+            sto(field_w<float>(g.lbar_out, b, a.nl, L, V), uv, tb[L]);
+            float *dd = field_w<float>(g.dbar, b, a.nl, L, V);
+            sto(dd, uv, ldf(dd, uv) - tb[L] * a.inv_c);
+        }
+    }
+}
+
+// ------------------------------------------------------ two kernels ------
+
+template <int ND, int NLMAX, int NNMAX, bool IDENT>
+__global__ __launch_bounds__(kBlock) void k_adj_flow(StepArgs a, AdjArgs g) {
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= a.V) return;
+    const int b = blockIdx.y;
+    const Coord c = coord_of(v, a.nx, a.ny);
+    const unsigned uv = (unsigned)v;
+    const size_t V = (size_t)a.V;
+    float out[NNMAX][ND], sb[NNMAX], e0[NLMAX], l0[NLMAX];
+    ka_point<ND, NLMAX, NNMAX, IDENT>(a, g, b, c, uv, out, sb, e0, l0);
+#pragma unroll
+    for (int A = 0; A < NNMAX; ++A) {
+        if (A < a.nn) {
+#pragma unroll
+            for (int k = 0; k < ND; ++k)
+                sto(field_w<float>(g.pbar_out, b, a.nn * ND, A * ND + k, V), uv, out[A][k]);
+        }
+    }
+    add_sbar<NNMAX>(a, g, b, uv, sb);
 }
 
 template <int ND, int NLMAX, int NNMAX, bool IDENT>
@@ -135,52 +237,129 @@ __global__ __launch_bounds__(kBlock) void k_adj_label(StepArgs a, AdjArgs g) {
     for (int L = 0; L < NLMAX; ++L) {
         const int Lc = L < a.nl ? L : a.nl - 1;
         e[L] = ldf(field<float>(g.ell_next, b, a.nl, Lc, V), uv);
-        lb[L] = ldf(field<float>(g.lbar, b, a.nl, Lc, V), uv);
+        lb[L] = ldf(field<float>(g.lbar_in, b, a.nl, Lc, V), uv);
     }
 #pragma unroll
     for (int A = 0; A < NNMAX; ++A) {
         const int Ac = A < a.nn ? A : a.nn - 1;
 #pragma unroll
+        for (int k = 0; k < 3; ++k) p0[A][k] = pm[A][k] = 0.f;
+#pragma unroll
         for (int k = 0; k < ND; ++k) {
-            const float *pk = field<float>(g.pbar, b, a.nn * ND, Ac * ND + k, V);
+            const float *pk = field<float>(g.pbar_out, b, a.nn * ND, Ac * ND + k, V);
             p0[A][k] = ldf(pk, uv);
             pm[A][k] = ldf(pk, uv - (unsigned)m[k]);
         }
     }
-    // ubar_L = sum_A W[A][L] * c tau div pbar_A
-    float ub[NLMAX];
+    float tb[NLMAX];
+    kb_point<ND, NLMAX, NNMAX, IDENT>(a, e, lb, p0, pm, fwd, bwd, tb);
+    store_label_adjoint<NLMAX>(a, g, b, uv, tb);
+}
+
+// ------------------------------------------------------ fused kernel -----
+
+template <int ND, int NLMAX, int NNMAX, bool IDENT>
+__global__ __launch_bounds__(RTHREADS) void k_adj_fused(StepArgs a, AdjArgs g, FusedGeom geo) {
+    // new pbar of the current plane: x components (column 0 = x0 - 1) and
+    // y components (row 0 = y0 - 1)
+    __shared__ float sx[NNMAX][RTY][RTX + 1];
+    __shared__ float sy[NNMAX][RTY + 1][RTX];
+    const int wave = threadIdx.x / RTX;
+    const int lane = threadIdx.x % RTX;
+
+    // XCD-aware block -> tile mapping (as in the fused forward kernel)
+    const int nb = gridDim.x;
+    const int pblk = blockIdx.x;
+    const int lblk = (nb % 8 == 0) ? (pblk % 8) * (nb / 8) + pblk / 8 : pblk;
+    const int bx = lblk % geo.tiles_x;
+    int r = lblk / geo.tiles_x;
+    const int by = r % geo.tiles_y;
+    r /= geo.tiles_y;
+    const int ch = r % geo.n_chunks;
+    const int b = r / geo.n_chunks;
+    const int x0 = bx * RTX, y0 = by * RTY;
+    const int zs = ch * geo.cz;
+    const int ze = min(a.nz, zs + geo.cz);
+    const size_t V = (size_t)a.V;
+
+    const bool halo = wave == RTY;
+    // point A: owned voxel column, or (halo wavefront) the row before the tile
+    const int xa = x0 + lane, ya = halo ? y0 - 1 : y0 + wave;
+    const bool va = xa < a.nx && ya >= 0 && ya < a.ny;
+    const bool own = !halo && va;
+    // point B (halo wavefront only): the column before the tile
+    const int xb = x0 - 1, yb = y0 + lane;
+    const bool vb = halo && lane < RTY && xb >= 0 && yb < a.ny;
+
+    float pz[NNMAX];                 // new pbar_z one plane below (owned points)
 #pragma unroll
-    for (int L = 0; L < NLMAX; ++L) ub[L] = 0.f;
+    for (int A = 0; A < NNMAX; ++A) pz[A] = 0.f;
+    if (ND == 3 && own && zs > 0) {
+        float out[NNMAX][ND], sb[NNMAX], e0[NLMAX], l0[NLMAX];
+        ka_point<ND, NLMAX, NNMAX, IDENT>(a, g, b, Coord{xa, ya, zs - 1},
+                                          (unsigned)(((zs - 1) * a.ny + ya) * a.nx + xa), out, sb,
+                                          e0, l0);
 #pragma unroll
-    for (int A = 0; A < NNMAX; ++A) {
-        const float dv = a.ctau * div_from<ND>(p0[A], pm[A], fwd, bwd);
-        if constexpr (IDENT) {
-            ub[A] += dv;
-        } else {
-#pragma unroll
-            for (int L = 0; L < NLMAX; ++L) ub[L] = fmaf(wgt(a, A, L), dv, ub[L]);
-        }
+        for (int A = 0; A < NNMAX; ++A) pz[A] = out[A][ND - 1];
     }
-    // adjoint of ell_{k+1} = t - LSE(t): tbar = gtot - u' sum(gtot)
-    float gt[NLMAX], sg = 0.f;
+
+    for (int z = zs; z < ze; ++z) {
+        float out[NNMAX][ND], sb[NNMAX], e0[NLMAX], l0[NLMAX];
+        const unsigned uva = (unsigned)((z * a.ny + ya) * a.nx + xa);
+        if (va) {
+            ka_point<ND, NLMAX, NNMAX, IDENT>(a, g, b, Coord{xa, ya, z}, uva, out, sb, e0, l0);
+            if (own) {
 #pragma unroll
-    for (int L = 0; L < NLMAX; ++L) {
-        const float u = __expf(e[L]);
-        gt[L] = L < a.nl ? fmaf(ub[L], u, lb[L]) : 0.f;
-        sg += gt[L];
-    }
+                for (int A = 0; A < NNMAX; ++A) {
+                    sx[A][wave][lane + 1] = out[A][0];
+                    sy[A][wave + 1][lane] = out[A][1];
+                }
+            } else {
 #pragma unroll
-    for (int L = 0; L < NLMAX; ++L) {
-        if (L < a.nl) {
-            const float tb = gt[L] - __expf(e[L]) * sg;
-            float *lo = field_w<float>(g.lbar, b, a.nl, L, V);
-            *reinterpret_cast<float *>(reinterpret_cast<char *>(lo) + uv * 4u) = tb;
-            float *dd = field_w<float>(g.dbar, b, a.nl, L, V);
-            float *dp = reinterpret_cast<float *>(reinterpret_cast<char *>(dd) + uv * 4u);
-            *dp -= tb * a.inv_c;
+                for (int A = 0; A < NNMAX; ++A) sy[A][0][lane] = out[A][1];
+            }
         }
+        if (vb) {
+            float ob[NNMAX][ND], sbb[NNMAX], eb[NLMAX], lbb[NLMAX];
+            ka_point<ND, NLMAX, NNMAX, IDENT>(a, g, b, Coord{xb, yb, z},
+                                              (unsigned)((z * a.ny + yb) * a.nx + xb), ob, sbb, eb,
+                                              lbb);
+#pragma unroll
+            for (int A = 0; A < NNMAX; ++A) sx[A][lane][0] = ob[A][0];
+        }
+        __syncthreads();
+        if (own) {
+            const bool fwd[3] = {xa < a.nx - 1, ya < a.ny - 1, ND == 3 && z < a.nz - 1};
+            const bool bwd[3] = {xa > 0, ya > 0, ND == 3 && z > 0};
+            float p0[NNMAX][3], pm[NNMAX][3];
+#pragma unroll
+            for (int A = 0; A < NNMAX; ++A) {
+                p0[A][0] = out[A][0];
+                p0[A][1] = out[A][1];
+                p0[A][2] = ND == 3 ? out[A][ND - 1] : 0.f;
+                pm[A][0] = sx[A][wave][lane];
+                pm[A][1] = sy[A][wave][lane];
+                pm[A][2] = pz[A];
+            }
+            float tb[NLMAX];
+            kb_point<ND, NLMAX, NNMAX, IDENT>(a, e0, l0, p0, pm, fwd, bwd, tb);
+            store_label_adjoint<NLMAX>(a, g, b, uva, tb);
+#pragma unroll
+            for (int A = 0; A < NNMAX; ++A) {
+                if (A < a.nn) {
+#pragma unroll
+                    for (int k = 0; k < ND; ++k)
+                        sto(field_w<float>(g.pbar_out, b, a.nn * ND, A * ND + k, V), uva, out[A][k]);
+                }
+                pz[A] = p0[A][2];
+            }
+            add_sbar<NNMAX>(a, g, b, uva, sb);
+        }
+        __syncthreads();
     }
 }
+
+// ------------------------------------------------------ utilities --------
 
 __global__ __launch_bounds__(kBlock) void k_fill(float *p, size_t n, float val) {
     const size_t stride = (size_t)gridDim.x * kBlock;
@@ -212,17 +391,6 @@ __global__ __launch_bounds__(kBlock) void k_sum_nodes(const float *sbar, int B, 
     if (threadIdx.x == 0) out[A] = (float)red[0];
 }
 
-// dS for a shared field: sum over nodes at every voxel.
-__global__ __launch_bounds__(kBlock) void k_sum_over_nodes(const float *sbar, int nn, size_t V,
-                                                           float *out) {
-    const int v = blockIdx.x * kBlock + threadIdx.x;
-    if ((size_t)v >= V) return;
-    const int b = blockIdx.y;
-    float s = 0.f;
-    for (int A = 0; A < nn; ++A) s += sbar[((size_t)b * nn + A) * V + v];
-    out[(size_t)b * V + v] = s;
-}
-
 unsigned sblocks(size_t n) {
     const size_t b = (n + kBlock - 1) / kBlock;
     return (unsigned)(b < 4096 ? (b ? b : 1) : 4096);
@@ -244,7 +412,28 @@ hipError_t adj_dispatch(int nd, bool ident, int nl, int nn, F &&f) {
     return nd == 2 ? by.template operator()<2>() : by.template operator()<3>();
 }
 
+// The fused reverse kernel keeps a point's whole adjoint state in registers
+// (twice on the halo wavefront); it is built for the buckets that fit in the
+// register budget of a 576-thread block without spilling: in 2-D Potts up to
+// 8 labels, in 3-D up to 4, and graphs up to 4 leaves / 8 flows.
+template <typename F>
+hipError_t adj_fused_dispatch(int nd, bool ident, int nl, F &&f) {
+    if (nd == 2) {
+        if (!ident) return f.template operator()<2, 4, 8, false>();
+        if (nl <= 4) return f.template operator()<2, 4, 4, true>();
+        return f.template operator()<2, 8, 8, true>();
+    }
+    if (!ident) return f.template operator()<3, 4, 8, false>();
+    return f.template operator()<3, 4, 4, true>();
+}
+
 }  // namespace
+
+bool adj_fused_supported(int nd, int nl, int nn, bool identity) {
+    if (nd == 2) return identity ? nl <= 8 : (nl <= 4 && nn <= 8);
+    if (nd == 3) return identity ? nl <= 4 : (nl <= 4 && nn <= 8);
+    return false;
+}
 
 hipError_t launch_adj_flow(const StepArgs &a, const AdjArgs &g, bool ident, int nd, hipStream_t s) {
     const dim3 grid((unsigned)((a.V + kBlock - 1) / kBlock), (unsigned)a.B, 1);
@@ -262,6 +451,16 @@ hipError_t launch_adj_label(const StepArgs &a, const AdjArgs &g, bool ident, int
     });
 }
 
+hipError_t launch_adj_fused(const StepArgs &a, const AdjArgs &g, bool ident, int nd, hipStream_t s) {
+    if (!adj_fused_supported(nd, a.nl, a.nn, ident)) return hipErrorInvalidValue;
+    const FusedGeom geo = fused_geometry(a);
+    if (geo.blocks <= 0 || geo.blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    return adj_fused_dispatch(nd, ident, a.nl, [&]<int ND, int NL, int NN, bool ID>() {
+        k_adj_fused<ND, NL, NN, ID><<<(unsigned)geo.blocks, RTHREADS, 0, s>>>(a, g, geo);
+        return hipGetLastError();
+    });
+}
+
 hipError_t launch_fill(float *p, size_t n, float val, hipStream_t s) {
     if (n == 0) return hipSuccess;
     k_fill<<<sblocks(n), kBlock, 0, s>>>(p, n, val);
@@ -274,16 +473,9 @@ hipError_t launch_copy_f(const float *a, float *b, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_sbar(const float *sbar, int B, int nn, size_t V, int s_mode, float *out,
-                              hipStream_t s) {
-    if (s_mode == PF_S_NODE_SCALAR) {
-        k_sum_nodes<<<nn, kBlock, 0, s>>>(sbar, B, nn, V, out);
-    } else if (s_mode == PF_S_SHARED_FIELD) {
-        k_sum_over_nodes<<<dim3((unsigned)((V + kBlock - 1) / kBlock), (unsigned)B), kBlock, 0, s>>>(
-            sbar, nn, V, out);
-    } else {
-        return launch_copy_f(sbar, out, (size_t)B * nn * V, s);
-    }
+hipError_t launch_sum_nodes(const float *sbar, int B, int nn, size_t V, float *out, hipStream_t s) {
+    if (nn < 1) return hipErrorInvalidValue;
+    k_sum_nodes<<<nn, kBlock, 0, s>>>(sbar, B, nn, V, out);
     return hipGetLastError();
 }
 

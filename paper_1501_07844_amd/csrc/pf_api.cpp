@@ -465,10 +465,11 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
     return PF_OK;
 }
 
-// Workspace of a backward call: results/flags/constants, then ckpt_every + 1
-// float32 segment states, pbar, lbar and the per-voxel capacity gradients.
+// Workspace of a backward call: constants, then ckpt_every + 1 float32
+// segment states, two pbar and two lbar buffers (ping-pong for the fused
+// reverse kernel) and the per-voxel capacity gradients of node constants.
 struct BwdLayout {
-    size_t consts, slots, pbar, lbar, sbar, total;
+    size_t consts, slots, pbar[2], lbar[2], sbar, total;
     TapeGeom tg;
 };
 
@@ -481,10 +482,14 @@ BwdLayout bwd_layout(const pf_grid &g, int nl, int nn, int every) {
     off = align256(off + sizeof(ConstBlock));
     L.slots = off;
     off += (size_t)(every + 1) * L.tg.slot_bytes;
-    L.pbar = off;
-    off = align256(off + (size_t)g.batch * nn * g.ndim * V * 4);
-    L.lbar = off;
-    off = align256(off + (size_t)g.batch * nl * V * 4);
+    for (int i = 0; i < 2; ++i) {
+        L.pbar[i] = off;
+        off = align256(off + (size_t)g.batch * nn * g.ndim * V * 4);
+    }
+    for (int i = 0; i < 2; ++i) {
+        L.lbar[i] = off;
+        off = align256(off + (size_t)g.batch * nl * V * 4);
+    }
     L.sbar = off;
     off = align256(off + (size_t)g.batch * nn * V * 4);
     L.total = off;
@@ -514,9 +519,16 @@ int run_backward(Prob &p, const pf_params *P, const float *grad_ell, float *grad
     auto slot_q = [&](int j) {
         return reinterpret_cast<float *>(ws + L.slots + (size_t)j * L.tg.slot_bytes + L.tg.ell_bytes);
     };
-    float *pbar = reinterpret_cast<float *>(ws + L.pbar);
-    float *lbar = reinterpret_cast<float *>(ws + L.lbar);
-    float *sbar = reinterpret_cast<float *>(ws + L.sbar);
+    float *pbar[2] = {reinterpret_cast<float *>(ws + L.pbar[0]), reinterpret_cast<float *>(ws + L.pbar[1])};
+    float *lbar[2] = {reinterpret_cast<float *>(ws + L.lbar[0]), reinterpret_cast<float *>(ws + L.lbar[1])};
+    // capacity gradient: fields accumulate straight into grad_S ([B][V] shared,
+    // [B][nn][V] per node); node constants per voxel first, summed at the end
+    const bool s_scalar = p.s_mode == PF_S_NODE_SCALAR;
+    float *sbar = s_scalar ? reinterpret_cast<float *>(ws + L.sbar) : grad_S;
+    const size_t n_sbar = (size_t)p.g.batch * (p.s_mode == PF_S_SHARED_FIELD ? 1 : p.nn) * V;
+    const bool fused = P->kernel != PF_KERNEL_TWO_PASS && adj_fused_supported(nd, p.nl, p.nn, p.ident);
+    if (P->kernel == PF_KERNEL_FUSED && !fused)
+        return fail(PF_EUNSUPPORTED, "fused reverse kernel unavailable for this problem");
 
     StepArgs a{};
     a.nx = p.g.nx;
@@ -551,10 +563,11 @@ int run_backward(Prob &p, const pf_params *P, const float *grad_ell, float *grad
         if ((e = launch_upload(cb, consts, stream)) != hipSuccess) return hip_fail(e, "upload");
     }
     if ((e = launch_fill(grad_D, n_ell, 0.f, stream)) != hipSuccess ||
-        (e = launch_fill(pbar, n_q, 0.f, stream)) != hipSuccess ||
-        (e = launch_fill(sbar, (size_t)p.g.batch * p.nn * V, 0.f, stream)) != hipSuccess ||
-        (e = launch_copy_f(grad_ell, lbar, n_ell, stream)) != hipSuccess)
+        (e = launch_fill(pbar[0], n_q, 0.f, stream)) != hipSuccess ||
+        (e = launch_fill(sbar, n_sbar, 0.f, stream)) != hipSuccess ||
+        (e = launch_copy_f(grad_ell, lbar[0], n_ell, stream)) != hipSuccess)
         return hip_fail(e, "backward init");
+    int cur = 0;
     const bool ident = p.ident;
     const int K = P->iters, k = P->ckpt_every;
     for (int seg = tg.slots - 1; seg >= 0; --seg) {
@@ -579,16 +592,29 @@ int run_backward(Prob &p, const pf_params *P, const float *grad_ell, float *grad
             AdjArgs g{};
             g.q_k = slot_q(j);
             g.ell_next = slot_ell(j + 1);
-            g.lbar = lbar;
-            g.pbar = pbar;
             g.sbar = sbar;
+            g.sbar_shared = p.s_mode == PF_S_SHARED_FIELD;
             g.dbar = grad_D;
             g.first = step == K - 1;
-            if ((e = launch_adj_flow(a, g, ident, nd, stream)) != hipSuccess) return hip_fail(e, "adjoint flow");
-            if ((e = launch_adj_label(a, g, ident, nd, stream)) != hipSuccess) return hip_fail(e, "adjoint label");
+            g.lbar_in = lbar[cur];
+            g.pbar_in = pbar[cur];
+            if (fused) {
+                g.lbar_out = lbar[1 - cur];
+                g.pbar_out = pbar[1 - cur];
+                if ((e = launch_adj_fused(a, g, ident, nd, stream)) != hipSuccess)
+                    return hip_fail(e, "fused reverse step");
+                cur = 1 - cur;
+            } else {
+                g.lbar_out = lbar[cur];
+                g.pbar_out = pbar[cur];
+                if ((e = launch_adj_flow(a, g, ident, nd, stream)) != hipSuccess)
+                    return hip_fail(e, "adjoint flow");
+                if ((e = launch_adj_label(a, g, ident, nd, stream)) != hipSuccess)
+                    return hip_fail(e, "adjoint label");
+            }
         }
     }
-    if ((e = launch_reduce_sbar(sbar, p.g.batch, p.nn, V, p.s_mode, grad_S, stream)) != hipSuccess)
+    if (s_scalar && (e = launch_sum_nodes(sbar, p.g.batch, p.nn, V, grad_S, stream)) != hipSuccess)
         return hip_fail(e, "capacity gradient");
     g_err.clear();
     return PF_OK;

@@ -63,14 +63,21 @@ struct Layout {
     size_t total;
 };
 
-// Buffers of one reverse step (float32).
+// Buffers of one reverse step (float32).  The two-kernel reverse step
+// updates lbar and pbar in place (in == out); the fused one reads the *_in
+// and writes the *_out buffers (ping-pong), since its halo points read
+// values that neighbouring blocks overwrite.
 struct AdjArgs {
     const float *q_k;        // flows entering step k [B][nn][nd][V]
     const float *ell_next;   // log-labels after step k [B][nl][V]
-    float *lbar;             // [B][nl][V], in/out
-    float *pbar;             // [B][nn][nd][V], in/out
-    float *sbar;             // [B][nn][V], accumulated
+    const float *lbar_in;    // [B][nl][V]
+    float *lbar_out;
+    const float *pbar_in;    // [B][nn][nd][V]
+    float *pbar_out;
+    float *sbar;             // accumulated capacity gradient: [B][V] (sum over
+                             // the flows) when sbar_shared, else [B][nn][V]
     float *dbar;             // [B][nl][V], accumulated (the caller's dD)
+    int32_t sbar_shared;
     int32_t first;           // last forward step: no later flow gradient
 };
 
@@ -104,9 +111,11 @@ hipError_t launch_check(const StepArgs &a, int32_t *flag, hipStream_t s);
 hipError_t launch_export_ell(const StepArgs &a, int storage, float *ell, hipStream_t s);
 hipError_t launch_adj_flow(const StepArgs &a, const AdjArgs &g, bool ident, int nd, hipStream_t s);
 hipError_t launch_adj_label(const StepArgs &a, const AdjArgs &g, bool ident, int nd, hipStream_t s);
+hipError_t launch_adj_fused(const StepArgs &a, const AdjArgs &g, bool ident, int nd, hipStream_t s);
+bool adj_fused_supported(int nd, int nl, int nn, bool identity);
 hipError_t launch_fill(float *p, size_t n, float val, hipStream_t s);
 hipError_t launch_copy_f(const float *a, float *b, size_t n, hipStream_t s);
-hipError_t launch_reduce_sbar(const float *sbar, int B, int nn, size_t V, int s_mode, float *out,
-                              hipStream_t s);
+// out[A] = sum over problems and voxels of sbar[B][nn][V] (fp64 accumulation)
+hipError_t launch_sum_nodes(const float *sbar, int B, int nn, size_t V, float *out, hipStream_t s);
 
 }  // namespace pf

@@ -39,10 +39,11 @@ def _oracle_grad(p, iters, weights, D=None, S=None):
     return ell.detach().numpy(), D.grad.numpy(), S.grad.numpy()
 
 
-def _gpu_grad(p, iters, ckpt, weights):
+def _gpu_grad(p, iters, ckpt, weights, backward_kernel="auto"):
     D = torch.from_numpy(np.ascontiguousarray(p.D)).cuda().requires_grad_(True)
     S = torch.from_numpy(np.ascontiguousarray(np.asarray(p.S, np.float32))).cuda().requires_grad_(True)
-    kw = dict(c=p.c, tau=p.tau, iters=iters, ckpt_every=ckpt, s_mode=p.s_mode, ndim=p.ndim)
+    kw = dict(c=p.c, tau=p.tau, iters=iters, ckpt_every=ckpt, s_mode=p.s_mode, ndim=p.ndim,
+              backward_kernel=backward_kernel)
     if p.kind == "potts":
         ell = pf.potts_layer(D, S, **kw)
     else:
@@ -61,6 +62,7 @@ def _cases():
     dag = synth.random_dag(rng, 3, 5)
     tree = synth.random_tree(rng, 2, 4)
     deep = synth.random_dag(rng, 9, 12)
+    small = synth.random_dag(rng, 3, 4)
     return {
         "potts2d_shared_B2": (synth.random_potts(11, (1, 37, 70), 2, 4, batch=2, s_mode="shared_field",
                                                  c=2.0, tau=0.125), 13, 5),
@@ -78,6 +80,12 @@ def _cases():
                                               c=4.0, tau=0.0625), 5, 2),
         "deep_dag3d_scalar": (synth.random_problem(18, (4, 6, 67), 3, deep, s_mode="node_scalar",
                                                    c=8.0, tau=1 / 12), 6, 4),
+        "dag2d_small_scalar": (synth.random_problem(19, (1, 19, 70), 2, small, s_mode="node_scalar",
+                                                    c=4.0, tau=0.0625), 7, 3),
+        "potts3d_chunked_nodefield": (synth.random_potts(20, (40, 10, 67), 3, 3, s_mode="node_field",
+                                                         c=1.0, tau=0.125), 4, 2),
+        "potts2d_nl8_shared": (synth.random_potts(21, (1, 17, 130), 2, 8, s_mode="shared_field",
+                                                  c=2.0, tau=0.125), 5, 2),
     }
 
 
@@ -94,6 +102,30 @@ def test_gradient_matches_oracle(name):
     print(f"{name}: max|dell|={de:.2e} rel dD={eD:.2e} rel dS={eS:.2e}", flush=True)
     assert de <= 1e-4
     assert eD <= G_RTOL and eS <= G_RTOL
+
+
+FUSED_BWD = ["potts2d_shared_B2", "potts3d_scalar", "potts2d_nodefield_nl5", "tree3d_scalar",
+             "dag2d_small_scalar", "potts3d_chunked_nodefield", "potts2d_nl8_shared"]
+
+
+@pytest.mark.parametrize("name", FUSED_BWD)
+def test_fused_reverse_equals_two_kernel_bitwise(name):
+    """The fused reverse step (tile + halo wavefront, ping-pong adjoints)
+    evaluates the same per-point expressions as the two-kernel step."""
+    p, iters, ckpt = CASES[name]
+    w = np.random.default_rng(3).standard_normal(p.D.shape).astype(np.float32)
+    a = _gpu_grad(p, iters, ckpt, w, backward_kernel="two_pass")
+    f = _gpu_grad(p, iters, ckpt, w, backward_kernel="fused")
+    for x, y in zip(a, f):
+        assert np.array_equal(x, y), float(np.abs(x - y).max())
+
+
+def test_fused_reverse_unsupported_bucket_is_reported():
+    p, iters, ckpt = CASES["potts3d_nl12"]
+    w = np.ones(p.D.shape, np.float32)
+    with pytest.raises(pf.PseudoflowError) as e:
+        _gpu_grad(p, iters, ckpt, w, backward_kernel="fused")
+    assert e.value.code == pf.PF_EUNSUPPORTED
 
 
 @pytest.mark.parametrize("name", ["potts2d_shared_B2", "dag2d_nodefield_B2"])
