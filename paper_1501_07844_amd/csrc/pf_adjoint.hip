@@ -19,8 +19,8 @@
 //     writes only its own voxel);
 //   * one fused kernel: a block owns an RTX x RTY tile of (x, y) columns and
 //     marches a chunk of z planes; the new pbar of the plane is exchanged
-//     through LDS, the points one column / one row before the tile are
-//     recomputed by an extra halo wavefront, and along z the backward
+//     through LDS, the points one row / one column before the tile are
+//     recomputed by two extra halo wavefronts, and along z the backward
 //     neighbour is the thread's own previous plane.  lbar and pbar are read
 //     from one buffer and written to another, since the halo points read
 //     values that the neighbouring blocks overwrite.
@@ -40,7 +40,7 @@ using namespace dev;
 
 constexpr int RTX = 64;               // tile width = one wavefront
 constexpr int RTY = 8;                // owned rows per tile (the fused forward tile)
-constexpr int RTHREADS = RTX * (RTY + 1);
+constexpr int RTHREADS = RTX * (RTY + 2);   // owned rows + two halo wavefronts
 
 // KA at voxel c (index uv) of problem b: the new pbar (out, 0 on the last
 // index of each axis and for padding flows), the capacity-gradient
@@ -158,40 +158,57 @@ __device__ __forceinline__ void kb_point(const StepArgs &a, const float (&e)[NLM
     for (int L = 0; L < NLMAX; ++L) tb[L] = gt[L] - u[L] * sg;
 }
 
-// Capacity gradient of one voxel: summed over the flows into one field when
-// every flow shares one capacity field, else one value per flow.
+// Capacity-gradient accumulator of one voxel: one field summed over the
+// flows when every flow shares one capacity field, else one value per flow.
+// Loaded ahead (with the other loads of the point), updated by add_sbar.
+template <int NNMAX>
+__device__ __forceinline__ void load_sbar(const StepArgs &a, const AdjArgs &g, int b, unsigned uv,
+                                          float (&acc)[NNMAX]) {
+    const size_t V = (size_t)a.V;
+#pragma unroll
+    for (int A = 0; A < NNMAX; ++A) {
+        const int f = g.sbar_shared ? 0 : (A < a.nn ? A : a.nn - 1);
+        acc[A] = ldf(field<float>(g.sbar, b, g.sbar_shared ? 1 : a.nn, f, V), uv);
+    }
+}
+
 template <int NNMAX>
 __device__ __forceinline__ void add_sbar(const StepArgs &a, const AdjArgs &g, int b, unsigned uv,
-                                         const float (&sb)[NNMAX]) {
+                                         const float (&acc)[NNMAX], const float (&sb)[NNMAX]) {
     const size_t V = (size_t)a.V;
     if (g.sbar_shared) {
         float s = 0.f;
 #pragma unroll
         for (int A = 0; A < NNMAX; ++A) s += sb[A];
-        float *p = field_w<float>(g.sbar, b, 1, 0, V);
-        sto(p, uv, ldf(p, uv) + s);
+        sto(field_w<float>(g.sbar, b, 1, 0, V), uv, acc[0] + s);
     } else {
 #pragma unroll
-        for (int A = 0; A < NNMAX; ++A) {
-            if (A < a.nn) {
-                float *p = field_w<float>(g.sbar, b, a.nn, A, V);
-                sto(p, uv, ldf(p, uv) + sb[A]);
-            }
-        }
+        for (int A = 0; A < NNMAX; ++A)
+            if (A < a.nn) sto(field_w<float>(g.sbar, b, a.nn, A, V), uv, acc[A] + sb[A]);
     }
+}
+
+// D-gradient accumulator of one voxel, loaded ahead.
+template <int NLMAX>
+__device__ __forceinline__ void load_dbar(const StepArgs &a, const AdjArgs &g, int b, unsigned uv,
+                                          float (&acc)[NLMAX]) {
+    const size_t V = (size_t)a.V;
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L)
+        acc[L] = ldf(field<float>(g.dbar, b, a.nl, L < a.nl ? L : a.nl - 1, V), uv);
 }
 
 // Stores of KB at an owned voxel: the new lbar, and D's gradient -= lbar / c.
 template <int NLMAX>
 __device__ __forceinline__ void store_label_adjoint(const StepArgs &a, const AdjArgs &g, int b,
-                                                    unsigned uv, const float (&tb)[NLMAX]) {
+                                                    unsigned uv, const float (&dacc)[NLMAX],
+                                                    const float (&tb)[NLMAX]) {
     const size_t V = (size_t)a.V;
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L) {
         if (L < a.nl) {
             sto(field_w<float>(g.lbar_out, b, a.nl, L, V), uv, tb[L]);
-            float *dd = field_w<float>(g.dbar, b, a.nl, L, V);
-            sto(dd, uv, ldf(dd, uv) - tb[L] * a.inv_c);
+            sto(field_w<float>(g.dbar, b, a.nl, L, V), uv, dacc[L] - tb[L] * a.inv_c);
         }
     }
 }
@@ -206,7 +223,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_flow(StepArgs a, AdjArgs g) {
     const Coord c = coord_of(v, a.nx, a.ny);
     const unsigned uv = (unsigned)v;
     const size_t V = (size_t)a.V;
-    float out[NNMAX][ND], sb[NNMAX], e0[NLMAX], l0[NLMAX];
+    float out[NNMAX][ND], sb[NNMAX], e0[NLMAX], l0[NLMAX], sacc[NNMAX];
+    load_sbar<NNMAX>(a, g, b, uv, sacc);
     ka_point<ND, NLMAX, NNMAX, IDENT>(a, g, b, c, uv, out, sb, e0, l0);
 #pragma unroll
     for (int A = 0; A < NNMAX; ++A) {
@@ -216,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_flow(StepArgs a, AdjArgs g) {
                 sto(field_w<float>(g.pbar_out, b, a.nn * ND, A * ND + k, V), uv, out[A][k]);
         }
     }
-    add_sbar<NNMAX>(a, g, b, uv, sb);
+    add_sbar<NNMAX>(a, g, b, uv, sacc, sb);
 }
 
 template <int ND, int NLMAX, int NNMAX, bool IDENT>
@@ -232,7 +250,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_label(StepArgs a, AdjArgs g) {
     backward_offsets(c, a, m, bwd);
     const bool fwd[3] = {c.x < a.nx - 1, c.y < a.ny - 1, ND == 3 && c.z < a.nz - 1};
 
-    float e[NLMAX], lb[NLMAX], p0[NNMAX][3], pm[NNMAX][3];
+    float e[NLMAX], lb[NLMAX], dacc[NLMAX], p0[NNMAX][3], pm[NNMAX][3];
+    load_dbar<NLMAX>(a, g, b, uv, dacc);
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L) {
         const int Lc = L < a.nl ? L : a.nl - 1;
@@ -253,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_label(StepArgs a, AdjArgs g) {
     }
     float tb[NLMAX];
     kb_point<ND, NLMAX, NNMAX, IDENT>(a, e, lb, p0, pm, fwd, bwd, tb);
-    store_label_adjoint<NLMAX>(a, g, b, uv, tb);
+    store_label_adjoint<NLMAX>(a, g, b, uv, dacc, tb);
 }
 
 // ------------------------------------------------------ fused kernel -----
@@ -282,14 +301,13 @@ __global__ __launch_bounds__(RTHREADS) void k_adj_fused(StepArgs a, AdjArgs g, F
     const int ze = min(a.nz, zs + geo.cz);
     const size_t V = (size_t)a.V;
 
-    const bool halo = wave == RTY;
-    // point A: owned voxel column, or (halo wavefront) the row before the tile
-    const int xa = x0 + lane, ya = halo ? y0 - 1 : y0 + wave;
-    const bool va = xa < a.nx && ya >= 0 && ya < a.ny;
-    const bool own = !halo && va;
-    // point B (halo wavefront only): the column before the tile
+    // point A: owned voxel column (waves 0 .. RTY-1), or the row before the
+    // tile (wave RTY); point B (wave RTY+1): the column before the tile
+    const int xa = x0 + lane, ya = wave == RTY ? y0 - 1 : y0 + wave;
+    const bool va = wave <= RTY && xa < a.nx && ya >= 0 && ya < a.ny;
+    const bool own = wave < RTY && va;
     const int xb = x0 - 1, yb = y0 + lane;
-    const bool vb = halo && lane < RTY && xb >= 0 && yb < a.ny;
+    const bool vb = wave == RTY + 1 && lane < RTY && xb >= 0 && yb < a.ny;
 
     float pz[NNMAX];                 // new pbar_z one plane below (owned points)
 #pragma unroll
@@ -304,8 +322,12 @@ __global__ __launch_bounds__(RTHREADS) void k_adj_fused(StepArgs a, AdjArgs g, F
     }
 
     for (int z = zs; z < ze; ++z) {
-        float out[NNMAX][ND], sb[NNMAX], e0[NLMAX], l0[NLMAX];
+        float out[NNMAX][ND], sb[NNMAX], e0[NLMAX], l0[NLMAX], dacc[NLMAX], sacc[NNMAX];
         const unsigned uva = (unsigned)((z * a.ny + ya) * a.nx + xa);
+        if (own) {
+            load_dbar<NLMAX>(a, g, b, uva, dacc);
+            load_sbar<NNMAX>(a, g, b, uva, sacc);
+        }
         if (va) {
             ka_point<ND, NLMAX, NNMAX, IDENT>(a, g, b, Coord{xa, ya, z}, uva, out, sb, e0, l0);
             if (own) {
@@ -343,7 +365,7 @@ __global__ __launch_bounds__(RTHREADS) void k_adj_fused(StepArgs a, AdjArgs g, F
             }
             float tb[NLMAX];
             kb_point<ND, NLMAX, NNMAX, IDENT>(a, e0, l0, p0, pm, fwd, bwd, tb);
-            store_label_adjoint<NLMAX>(a, g, b, uva, tb);
+            store_label_adjoint<NLMAX>(a, g, b, uva, dacc, tb);
 #pragma unroll
             for (int A = 0; A < NNMAX; ++A) {
                 if (A < a.nn) {
@@ -353,7 +375,7 @@ __global__ __launch_bounds__(RTHREADS) void k_adj_fused(StepArgs a, AdjArgs g, F
                 }
                 pz[A] = p0[A][2];
             }
-            add_sbar<NNMAX>(a, g, b, uva, sb);
+            add_sbar<NNMAX>(a, g, b, uva, sacc, sb);
         }
         __syncthreads();
     }
@@ -414,8 +436,8 @@ hipError_t adj_dispatch(int nd, bool ident, int nl, int nn, F &&f) {
 
 // The fused reverse kernel keeps a point's whole adjoint state in registers
 // (twice on the halo wavefront); it is built for the buckets that fit in the
-// register budget of a 576-thread block without spilling: in 2-D Potts up to
-// 8 labels, in 3-D up to 4, and graphs up to 4 leaves / 8 flows.
+// register budget of a 640-thread block without spilling: Potts up to 8
+// labels in 2-D and 4 in 3-D, label graphs up to 4 leaves / 8 flows in 2-D.
 template <typename F>
 hipError_t adj_fused_dispatch(int nd, bool ident, int nl, F &&f) {
     if (nd == 2) {
@@ -423,7 +445,6 @@ hipError_t adj_fused_dispatch(int nd, bool ident, int nl, F &&f) {
         if (nl <= 4) return f.template operator()<2, 4, 4, true>();
         return f.template operator()<2, 8, 8, true>();
     }
-    if (!ident) return f.template operator()<3, 4, 8, false>();
     return f.template operator()<3, 4, 4, true>();
 }
 
@@ -431,7 +452,7 @@ hipError_t adj_fused_dispatch(int nd, bool ident, int nl, F &&f) {
 
 bool adj_fused_supported(int nd, int nl, int nn, bool identity) {
     if (nd == 2) return identity ? nl <= 8 : (nl <= 4 && nn <= 8);
-    if (nd == 3) return identity ? nl <= 4 : (nl <= 4 && nn <= 8);
+    if (nd == 3) return identity && nl <= 4;
     return false;
 }
 
@@ -453,7 +474,7 @@ hipError_t launch_adj_label(const StepArgs &a, const AdjArgs &g, bool ident, int
 
 hipError_t launch_adj_fused(const StepArgs &a, const AdjArgs &g, bool ident, int nd, hipStream_t s) {
     if (!adj_fused_supported(nd, a.nl, a.nn, ident)) return hipErrorInvalidValue;
-    const FusedGeom geo = fused_geometry(a);
+    const FusedGeom geo = tile_geometry(a, RTY);
     if (geo.blocks <= 0 || geo.blocks > 0x7fffffffL) return hipErrorInvalidValue;
     return adj_fused_dispatch(nd, ident, a.nl, [&]<int ND, int NL, int NN, bool ID>() {
         k_adj_fused<ND, NL, NN, ID><<<(unsigned)geo.blocks, RTHREADS, 0, s>>>(a, g, geo);

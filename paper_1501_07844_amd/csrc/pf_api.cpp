@@ -465,9 +465,10 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
     return PF_OK;
 }
 
-// Workspace of a backward call: constants, then ckpt_every + 1 float32
-// segment states, two pbar and two lbar buffers (ping-pong for the fused
-// reverse kernel) and the per-voxel capacity gradients of node constants.
+// Workspace of a backward call: constants, then ckpt_every float32 segment
+// states (the states after the checkpoint; the checkpoint itself is read from
+// the tape), two pbar and two lbar buffers (ping-pong for the fused reverse
+// kernel) and the per-voxel capacity gradients of node constants.
 struct BwdLayout {
     size_t consts, slots, pbar[2], lbar[2], sbar, total;
     TapeGeom tg;
@@ -481,7 +482,7 @@ BwdLayout bwd_layout(const pf_grid &g, int nl, int nn, int every) {
     L.consts = off;
     off = align256(off + sizeof(ConstBlock));
     L.slots = off;
-    off += (size_t)(every + 1) * L.tg.slot_bytes;
+    off += (size_t)every * L.tg.slot_bytes;
     for (int i = 0; i < 2; ++i) {
         L.pbar[i] = off;
         off = align256(off + (size_t)g.batch * nn * g.ndim * V * 4);
@@ -572,26 +573,34 @@ int run_backward(Prob &p, const pf_params *P, const float *grad_ell, float *grad
     const int K = P->iters, k = P->ckpt_every;
     for (int seg = tg.slots - 1; seg >= 0; --seg) {
         const int k0 = seg * k, k1 = std::min(K, k0 + k), m = k1 - k0;
+        // state j of the segment: the checkpoint itself (read in place) for
+        // j == 0, else the recomputed slot j - 1
         const char *src = static_cast<const char *>(P->tape) + (size_t)seg * tg.slot_bytes;
-        if ((e = launch_copy_f(reinterpret_cast<const float *>(src), slot_ell(0), n_ell, stream)) != hipSuccess ||
-            (e = launch_copy_f(reinterpret_cast<const float *>(src + tg.ell_bytes), slot_q(0), n_q, stream)) !=
-                hipSuccess)
-            return hip_fail(e, "segment restore");
-        for (int j = 0; j < m; ++j) {   // recompute the segment's states, out of place
+        auto st_ell = [&](int j) {
+            return j == 0 ? const_cast<float *>(reinterpret_cast<const float *>(src)) : slot_ell(j - 1);
+        };
+        auto st_q = [&](int j) {
+            return j == 0 ? const_cast<float *>(reinterpret_cast<const float *>(src + tg.ell_bytes))
+                          : slot_q(j - 1);
+        };
+        // recompute the segment's states out of place; the reverse steps read
+        // ell_1 .. ell_m and q_0 .. q_{m-1}, so the last flow step is skipped
+        for (int j = 0; j < m; ++j) {
             StepArgs f = a;
-            f.ell_in = slot_ell(j);
-            f.q_in = slot_q(j);
-            f.ell_out = slot_ell(j + 1);
+            f.ell_in = st_ell(j);
+            f.q_in = st_q(j);
+            f.ell_out = st_ell(j + 1);
             if ((e = launch_label(f, ident, nd, PF_FP32, stream)) != hipSuccess) return hip_fail(e, "recompute");
-            f.ell_in = slot_ell(j + 1);
-            f.q_out = slot_q(j + 1);
+            if (j + 1 == m) break;
+            f.ell_in = st_ell(j + 1);
+            f.q_out = st_q(j + 1);
             if ((e = launch_flow(f, ident, nd, PF_FP32, stream)) != hipSuccess) return hip_fail(e, "recompute");
         }
         for (int step = k1 - 1; step >= k0; --step) {
             const int j = step - k0;
             AdjArgs g{};
-            g.q_k = slot_q(j);
-            g.ell_next = slot_ell(j + 1);
+            g.q_k = st_q(j);
+            g.ell_next = st_ell(j + 1);
             g.sbar = sbar;
             g.sbar_shared = p.s_mode == PF_S_SHARED_FIELD;
             g.dbar = grad_D;

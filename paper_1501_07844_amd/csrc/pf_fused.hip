@@ -10,9 +10,10 @@
 // chunk of z planes.  Along z the forward neighbour is the thread's own next
 // plane (kept in registers, together with the old q_z of the previous plane
 // for the divergence).  Along x and y the new labels of the plane are
-// exchanged through LDS; the labels one column past the tile (x) and one row
-// past it (y) belong to the neighbouring tiles and are recomputed here by one
-// extra "halo" wavefront.  Each point's label step, flow step and rounding
+// exchanged through LDS; the labels one row past the tile (y) and one column
+// past it (x) belong to the neighbouring tiles and are recomputed here by two
+// extra "halo" wavefronts (one each, so that no wavefront evaluates two
+// points per plane and the barrier waits for one round of loads).  Each point's label step, flow step and rounding
 // are the expressions of the two-pass kernels, so both variants give the same
 // state bit for bit.
 //
@@ -33,7 +34,7 @@ using namespace dev;
 
 constexpr int FTX = 64;               // tile width = one wavefront
 constexpr int FTY = 8;                // owned rows per tile
-constexpr int FTHREADS = FTX * (FTY + 1);
+constexpr int FTHREADS = FTX * (FTY + 2);   // owned rows + two halo wavefronts
 
 // Label step at voxel (x, y, z) of problem b.  qzb holds the old q_z of every
 // flow one plane below (ignored at z == 0).  Returns the new labels as the
@@ -104,14 +105,13 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
     const int zs = ch * g.cz;
     const int ze = min(a.nz, zs + g.cz);
 
-    const bool halo = wave == FTY;
-    // point A: owned voxel column, or the halo row past the tile
+    // point A: owned voxel column (waves 0 .. FTY-1), or the halo row past
+    // the tile (wave FTY); point B (wave FTY+1): the column past the tile
     const int xa = x0 + lane, ya = y0 + wave;
-    const bool va = xa < a.nx && ya < a.ny;
-    const bool own = !halo && va;
-    // point B (halo wavefront only): the column past the tile
+    const bool va = wave <= FTY && xa < a.nx && ya < a.ny;
+    const bool own = wave < FTY && va;
     const int xb = x0 + FTX, yb = y0 + lane;
-    const bool vb = halo && lane < FTY && xb < a.nx && yb < a.ny;
+    const bool vb = wave == FTY + 1 && lane < FTY && xb < a.nx && yb < a.ny;
 
     const size_t V = (size_t)a.V;
 
@@ -152,6 +152,13 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
 
     for (int z = zs; z < ze; ++z) {
         const bool has_next = z + 1 < a.nz;
+        // capacities of the owned voxel, loaded ahead of the label step
+        float sv[NNMAX];
+        if (own) {
+            const int v = (z * a.ny + ya) * a.nx + xa;
+#pragma unroll
+            for (int A = 0; A < NNMAX; ++A) sv[A] = smooth(a, b, A < a.nn ? A : a.nn - 1, v);
+        }
         float un[NLMAX], qn[NNMAX][ND], ubn[NLMAX];
 #pragma unroll
         for (int L = 0; L < NLMAX; ++L) un[L] = ubn[L] = ua[L];   // defined when !has_next
@@ -173,9 +180,6 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
         if (own) {
             const int v = (z * a.ny + ya) * a.nx + xa;
             const bool h[3] = {xa < a.nx - 1, ya < a.ny - 1, ND == 3 && has_next};
-            float sv[NNMAX];
-#pragma unroll
-            for (int A = 0; A < NNMAX; ++A) sv[A] = smooth(a, b, A < a.nn ? A : a.nn - 1, v);
             float gu[NLMAX][ND];
 #pragma unroll
             for (int L = 0; L < NLMAX; ++L) {
@@ -257,10 +261,12 @@ bool fused_preferred(int nd, int nl, int nn, bool identity, int storage) {
     return identity && nd == 3 && storage == PF_FP32 && fused_supported(nd, nl, nn, identity);
 }
 
-FusedGeom fused_geometry(const StepArgs &a) {
+FusedGeom fused_geometry(const StepArgs &a) { return tile_geometry(a, FTY); }
+
+FusedGeom tile_geometry(const StepArgs &a, int rows) {
     FusedGeom g{};
     g.tiles_x = (a.nx + FTX - 1) / FTX;
-    g.tiles_y = (a.ny + FTY - 1) / FTY;
+    g.tiles_y = (a.ny + rows - 1) / rows;
     const long tiles = (long)g.tiles_x * g.tiles_y * a.B;
     // aim for about two resident blocks per compute unit on 256 CUs, with
     // chunks of at least 16 planes (each chunk recomputes one extra plane)

@@ -229,9 +229,9 @@ def test_binding_refuses_cpu_tensors():
 
 def test_tape_and_backward_workspace_accounting():
     """One float32 state (labels, then flows, each 256-byte aligned) per
-    checkpoint, ceil(K / k) checkpoints; the backward workspace holds k + 1
-    segment states, two adjoint flow and two adjoint label states
-    (ping-pong) and the per-flow capacity gradients."""
+    checkpoint, ceil(K / k) checkpoints; the backward workspace holds the k
+    recomputed states of a segment, two adjoint flow and two adjoint label
+    states (ping-pong) and the per-flow capacity gradients."""
     lib = pf.library()
     g = _grid(2, 3, 8, 9, 10)
     V = 8 * 9 * 10
@@ -242,7 +242,7 @@ def test_tape_and_backward_workspace_accounting():
     for k in (1, 4, 10):
         n = lib.pf_backward_workspace_bytes(C.byref(g), 4, 6, k)
         adj = 2 * al(2 * 6 * 3 * V * 4) + 2 * al(2 * 4 * V * 4) + al(2 * 6 * V * 4)
-        assert (k + 1) * slot + adj <= n <= (k + 1) * slot + adj + 64 * 1024
+        assert k * slot + adj <= n <= k * slot + adj + 64 * 1024
     assert lib.pf_tape_bytes(C.byref(g), 4, 6, 10, 0) == 0
     assert lib.pf_tape_bytes(C.byref(g), 4, 6, -1, 2) == 0
     assert lib.pf_tape_bytes(C.byref(g), 17, 6, 10, 2) == 0

@@ -104,7 +104,7 @@ def test_gradient_matches_oracle(name):
     assert eD <= G_RTOL and eS <= G_RTOL
 
 
-FUSED_BWD = ["potts2d_shared_B2", "potts3d_scalar", "potts2d_nodefield_nl5", "tree3d_scalar",
+FUSED_BWD = ["potts2d_shared_B2", "potts3d_scalar", "potts2d_nodefield_nl5",
              "dag2d_small_scalar", "potts3d_chunked_nodefield", "potts2d_nl8_shared"]
 
 
@@ -120,8 +120,9 @@ def test_fused_reverse_equals_two_kernel_bitwise(name):
         assert np.array_equal(x, y), float(np.abs(x - y).max())
 
 
-def test_fused_reverse_unsupported_bucket_is_reported():
-    p, iters, ckpt = CASES["potts3d_nl12"]
+@pytest.mark.parametrize("name", ["potts3d_nl12", "tree3d_scalar"])
+def test_fused_reverse_unsupported_bucket_is_reported(name):
+    p, iters, ckpt = CASES[name]
     w = np.ones(p.D.shape, np.float32)
     with pytest.raises(pf.PseudoflowError) as e:
         _gpu_grad(p, iters, ckpt, w, backward_kernel="fused")
