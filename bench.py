@@ -1,16 +1,22 @@
-"""Throughput of the pseudo-flow Potts solve on one MI355X.
+"""Throughput of the pseudo-flow solvers on one MI355X.
 
-Workload: Potts 3-D, 256^3 voxels, 8 labels, float32 state and arithmetic,
-500 iterations (seeded 64-site Voronoi phantom, noise 0.15, Gaussian-NLL data
-terms, S(x) = 0.3 exp(-|grad I|^2 / 0.01)).  One step is one complete solve:
-initialisation, 500 iterations, the float64 energy/dual/gap evaluation and the
-argmax export.  Inputs are resident in HBM before timing starts.
+Headline workload: Potts 3-D, 256^3 voxels, 8 labels, float32 state and
+arithmetic, 500 iterations (seeded 64-site Voronoi phantom, noise 0.15,
+Gaussian-NLL data terms, S(x) = 0.3 exp(-|grad I|^2 / 0.01)).  One step is one
+complete solve: initialisation, 500 iterations, the float64 energy/dual/gap
+evaluation and the argmax export.  Inputs are resident in HBM before timing
+starts.
 
 Prints one JSON line: voxel-label iterations per second (voxel-label = voxels
-x non-source label nodes), the roofline of the per-iteration kernel measured
-with HIP events inside the timed region, the same solve with bf16 state
-storage, and the float64 reference implementation timed on a bounded sample
-on the host.
+x non-source label nodes) of the headline solve; the roofline of its
+per-iteration kernel, timed with HIP events inside the timed region; the
+per-iteration kernel rates of every workload (Potts 2-D and 3-D, HMF, DAGMF;
+float32 and bf16 state); a plain device copy as the achievable bandwidth;
+the cost of the differentiable solve; and the float64 reference
+implementation timed on a bounded sample on the host.
+
+``--counters`` runs only a short program for rocprofv3 counter passes: a
+device copy of known size, then a few iterations of the headline kernel.
 """
 from __future__ import annotations
 
@@ -27,6 +33,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 ITERS = 500
+COPY_BYTES = 1 << 30          # the copy kernel moves 1 GiB in and 1 GiB out
 
 
 def _kernel_source_hash() -> str:
@@ -51,110 +58,76 @@ def _traffic(kernel: str, source_hash: str):
     return rec.get("bytes_per_launch")
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")
-    ap.add_argument("--kernel", default="auto", choices=["auto", "two_pass", "fused"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-bf16", action="store_true")
-    ap.add_argument("--no-adjoint", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
-              "z-slab design is not built", file=sys.stderr)
-        return 2
+def bytes_alg(p, storage: str) -> int:
+    """Algorithmic HBM bytes per voxel and iteration: every state field read
+    and written once, the data terms and capacity fields read once."""
+    s = 4 if storage == "fp32" else 2
+    s_fields = {"node_scalar": 0, "shared_field": 1, "node_field": p.n_node}[p.s_mode]
+    return 2 * s * (p.n_leaf + p.ndim * p.n_node) + 4 * p.n_leaf + 4 * s_fields
 
+
+def _inputs(p, dev):
     import numpy as np
     import torch
-
-    import paper_1501_07844_amd as pf
-    from paper_1501_07844_amd import synth
-
-    t0 = time.time()
-    p = synth.potts3d_voronoi(n=args.n, iters=ITERS)
-    print(f"[bench] inputs {p.shape} x {p.n_leaf} labels generated in {time.time() - t0:.1f}s",
-          file=sys.stderr, flush=True)
-    dev = torch.device("cuda:0")
     D = torch.from_numpy(p.D).to(dev)
-    S = torch.from_numpy(p.S).to(dev)
-    B, Z, Y, X = p.shape
-    V = B * Z * Y * X
-    n_node = p.n_node
-    kw = dict(c=p.c, tau=p.tau, iters=ITERS, ndim=3, s_mode="shared_field",
-              kernel=args.kernel, final_energy=True, return_u=False, return_labels=True)
+    S = np.asarray(p.S) if p.s_mode == "node_scalar" else torch.from_numpy(p.S).to(dev)
+    return D, S
 
-    def run_steps(storage, steps, warmup, timing_stride):
-        ws = None
-        res = None
-        for _ in range(warmup):
-            res = pf.solve_potts(D, S, storage=storage, workspace=ws, **kw)
-            ws = res.workspace
-        torch.cuda.synchronize()
-        kernel_ms, kernel_n = 0.0, 0
-        t_start = time.perf_counter()
-        for _ in range(steps):
-            res = pf.solve_potts(D, S, storage=storage, workspace=ws,
-                                 timing_stride=timing_stride, **kw)
-            ws = res.workspace
-            kernel_ms += res.kernel_ms
-            kernel_n += res.kernel_timed
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t_start
-        return res, elapsed, kernel_ms, kernel_n
 
-    res, elapsed, kms, kn = run_steps("fp32", args.steps, args.warmup, timing_stride=25)
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = V * n_node * ITERS * args.steps / elapsed
-    print(f"[bench] fp32: {ms_per_step:.1f} ms/step, energy {res.energy:.6e}, gap {res.gap:.3e}",
-          file=sys.stderr, flush=True)
+def _solver(pf, p):
+    if p.kind == "potts":
+        return lambda D, S, **kw: pf.solve_potts(D, S, **kw)
+    if p.kind == "hmf":
+        return lambda D, S, **kw: pf.solve_hmf(D, S, p.graph, **kw)
+    return lambda D, S, **kw: pf.solve_dagmf(D, S, p.graph, **kw)
 
-    fused = args.kernel == "fused" or (args.kernel == "auto" and res.workspace.numel() >
-                                       pf.workspace_bytes(p.shape, p.n_leaf, n_node, 3, "fp32",
-                                                          "two_pass"))
-    kernel_name = "k_fused" if fused else "k_label+k_flow"
-    bytes_alg = (2 * 4 * (p.n_leaf + 3 * n_node) + 4 * p.n_leaf + 4) * V   # per iteration
-    avg_ms = kms / max(kn, 1)
-    achieved = bytes_alg / (avg_ms * 1e-3) / 1e9
-    src_hash = _kernel_source_hash()
-    traffic = _traffic(kernel_name, src_hash)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": kernel_name, "kernel_avg_ms": round(avg_ms, 4),
-                "kernel_launches_timed": kn, "algorithmic_bytes_per_launch": bytes_alg}
 
-    out = {
-        "metric": "voxel-label iterations/s (Potts 3D 256^3, 8 labels, fp32)",
-        "value": value, "unit": "voxel-label-iterations/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (seeded Voronoi phantom)",
-        "config": {"workload": f"potts3d_voronoi {Z}x{Y}x{X}, 8 labels, {ITERS} iterations, "
-                               f"c={p.c}, tau={p.tau}, fp32 state",
-                   "voxels": V, "labels": p.n_leaf, "iterations": ITERS,
-                   "kernel": args.kernel, "energy": res.energy, "gap": res.gap},
-        "roofline": roofline,
-    }
+def kernel_leg(p, storage: str, iters: int, dev, kernel: str = "auto") -> dict:
+    """Per-iteration kernel time of one workload: one warm-up solve, then a
+    solve with every iteration bracketed by HIP events on the solver's
+    stream; the mean over the iterations."""
+    import paper_1501_07844_amd as pf
+    D, S = _inputs(p, dev)
+    solve = _solver(pf, p)
+    kw = dict(c=p.c, tau=p.tau, iters=iters, ndim=p.ndim, s_mode=p.s_mode, storage=storage,
+              kernel=kernel, final_energy=True, return_u=False, return_labels=False)
+    r = solve(D, S, **kw)
+    r = solve(D, S, workspace=r.workspace, timing_stride=1, **kw)
+    ms = r.kernel_ms / max(r.kernel_timed, 1)
+    fused = r.workspace.numel() > pf.workspace_bytes(p.shape, p.n_leaf, p.n_node, p.ndim,
+                                                     storage, "two_pass")
+    V = p.voxels
+    ba = bytes_alg(p, storage)
+    achieved = ba * V / (ms * 1e-3) / 1e9
+    out = {"workload": f"{p.name} {'x'.join(map(str, p.shape[1:]))}"
+                       + (f" x{p.shape[0]}" if p.shape[0] > 1 else ""),
+           "storage": storage, "kernel": "k_fused" if fused else "k_label+k_flow",
+           "ms_per_iter": round(ms, 4), "iterations_timed": r.kernel_timed,
+           "voxel_label_its_per_s": V * p.n_node / (ms * 1e-3),
+           "alg_bytes_per_voxel": ba, "alg_GBs": round(achieved, 1),
+           "hbm_frac": round(achieved / HBM_PEAK_GBS, 4), "energy": r.energy}
+    del D, S, r
+    return out
 
-    if not args.no_bf16:
-        rb, eb, kmsb, knb = run_steps("bf16", args.steps, args.warmup, timing_stride=25)
-        vb = V * n_node * ITERS * args.steps / eb
-        out["bf16_storage"] = {
-            "value": vb, "ratio_vs_fp32": vb / value,
-            "rel_energy_vs_fp32": abs(rb.energy - res.energy) / abs(res.energy),
-            "kernel_avg_ms": round(kmsb / max(knb, 1), 4), "ms_per_step": 1e3 * eb / args.steps}
-        print(f"[bench] bf16: {1e3 * eb / args.steps:.1f} ms/step", file=sys.stderr, flush=True)
 
-    if not args.no_adjoint:
-        out["adjoint"] = adjoint_leg(dev)
-
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p)
-
-    print(json.dumps(out), flush=True)
-    return 0
+def copy_leg(dev) -> dict:
+    """Achievable bandwidth: a plain device-to-device copy of 1 GiB (read +
+    write bytes over the kernel time), median of 5 after a warm-up."""
+    import torch
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    ts = []
+    for i in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        if i:
+            ts.append(e0.elapsed_time(e1))
+    ms = sorted(ts)[len(ts) // 2]
+    return {"bytes": 2 * COPY_BYTES, "ms": round(ms, 4),
+            "GBs": round(2 * COPY_BYTES / (ms * 1e-3) / 1e9, 1)}
 
 
 def adjoint_leg(dev, reps: int = 3) -> dict:
@@ -210,6 +183,169 @@ def adjoint_leg(dev, reps: int = 3) -> dict:
                         f"every {k}, fp32", "forward_ms": round(f, 3),
             "forward_recorded_ms": round(r, 3), "backward_ms": round(b, 3),
             "backward_over_forward": round(b / f, 3), "total_over_forward": round((r + b) / f, 3)}
+
+
+def potts2d_leg(dev, reps: int = 5) -> dict:
+    """The small 2-D Potts case (64 x 64, 3 labels, 200 iterations): whole
+    solves per second, median of `reps` (latency-bound, cache-resident)."""
+    import torch
+
+    import paper_1501_07844_amd as pf
+    from paper_1501_07844_amd import synth
+    p = synth.potts2d_rects()
+    D, S = _inputs(p, dev)
+    kw = dict(c=p.c, tau=p.tau, iters=p.iters, s_mode=p.s_mode, ndim=2, final_energy=True)
+    r = pf.solve_potts(D, S, **kw)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = pf.solve_potts(D, S, workspace=r.workspace, **kw)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    t = sorted(ts)[len(ts) // 2]
+    return {"workload": "potts2d_rects 64x64, 3 labels, 200 iterations, fp32",
+            "ms_per_solve": round(1e3 * t, 3), "iterations_per_s": round(p.iters / t, 1),
+            "energy": r.energy, "gap": r.gap}
+
+
+def counters_program() -> int:
+    """Short program for rocprofv3 counter passes: one copy of COPY_BYTES
+    (the calibration kernel), then 5 iterations of the headline solve."""
+    import torch
+
+    import paper_1501_07844_amd as pf
+    from paper_1501_07844_amd import synth
+    dev = torch.device("cuda:0")
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    p = synth.potts3d_voronoi(n=256, iters=5)
+    D, S = _inputs(p, dev)
+    r = pf.solve_potts(D, S, c=p.c, tau=p.tau, iters=5, ndim=3, s_mode=p.s_mode,
+                       final_energy=False, return_u=False, return_labels=False)
+    torch.cuda.synchronize()
+    print(json.dumps({"counters_program": "done", "iters": r.iters_done,
+                      "source_hash": _kernel_source_hash()}), flush=True)
+    return 0
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "two_pass", "fused"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--counters", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
+              "z-slab design is not built", file=sys.stderr)
+        return 2
+    if args.counters:
+        return counters_program()
+
+    import torch
+
+    import paper_1501_07844_amd as pf
+    from paper_1501_07844_amd import synth
+
+    t0 = time.time()
+    p = synth.potts3d_voronoi(n=args.n, iters=ITERS)
+    print(f"[bench] inputs {p.shape} x {p.n_leaf} labels generated in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    D = torch.from_numpy(p.D).to(dev)
+    S = torch.from_numpy(p.S).to(dev)
+    B, Z, Y, X = p.shape
+    V = B * Z * Y * X
+    n_node = p.n_node
+    kw = dict(c=p.c, tau=p.tau, iters=ITERS, ndim=3, s_mode="shared_field",
+              kernel=args.kernel, final_energy=True, return_u=False, return_labels=True)
+
+    ws = None
+    res = None
+    for _ in range(args.warmup):
+        res = pf.solve_potts(D, S, workspace=ws, **kw)
+        ws = res.workspace
+    torch.cuda.synchronize()
+    kms, kn = 0.0, 0
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        res = pf.solve_potts(D, S, workspace=ws, timing_stride=25, **kw)
+        ws = res.workspace
+        kms += res.kernel_ms
+        kn += res.kernel_timed
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = V * n_node * ITERS * args.steps / elapsed
+    print(f"[bench] fp32: {ms_per_step:.1f} ms/step, energy {res.energy:.6e}, gap {res.gap:.3e}",
+          file=sys.stderr, flush=True)
+
+    fused = res.workspace.numel() > pf.workspace_bytes(p.shape, p.n_leaf, n_node, 3, "fp32",
+                                                       "two_pass")
+    kernel_name = "k_fused" if fused else "k_label+k_flow"
+    ba = bytes_alg(p, "fp32") * V                                  # per launch (iteration)
+    avg_ms = kms / max(kn, 1)
+    achieved = ba / (avg_ms * 1e-3) / 1e9
+    src_hash = _kernel_source_hash()
+    traffic = _traffic(kernel_name, src_hash)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": kernel_name, "kernel_avg_ms": round(avg_ms, 4),
+                "kernel_launches_timed": kn, "algorithmic_bytes_per_launch": ba,
+                "source_hash": src_hash}
+    del D, S, ws, res
+
+    out = {
+        "metric": "voxel-label iterations/s (Potts 3D 256^3, 8 labels, fp32)",
+        "value": value, "unit": "voxel-label-iterations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded Voronoi phantom)",
+        "config": {"workload": f"potts3d_voronoi {Z}x{Y}x{X}, 8 labels, {ITERS} iterations, "
+                               f"c={p.c}, tau={p.tau}, fp32 state",
+                   "voxels": V, "labels": p.n_leaf, "iterations": ITERS,
+                   "kernel": args.kernel},
+        "roofline": roofline,
+    }
+    out["copy_peak"] = copy_leg(dev)
+    torch.cuda.empty_cache()
+
+    if not args.no_workloads:
+        legs = []
+        for make, iters in ((lambda: synth.potts3d_voronoi(n=args.n), 20),
+                            (synth.hmf_ellipsoids, 20), (synth.dagmf_blobs, 10)):
+            q = make()
+            for storage in ("fp32", "bf16"):
+                leg = kernel_leg(q, storage, iters, dev)
+                print(f"[bench] {leg['workload']} {storage}: {leg['ms_per_iter']} ms/iter, "
+                      f"{leg['alg_GBs']} GB/s alg", file=sys.stderr, flush=True)
+                legs.append(leg)
+                torch.cuda.empty_cache()
+            del q
+        for i in range(0, len(legs), 2):
+            legs[i + 1]["speedup_vs_fp32"] = round(legs[i]["ms_per_iter"] / legs[i + 1]["ms_per_iter"], 3)
+            legs[i + 1]["rel_energy_vs_fp32"] = abs(legs[i + 1]["energy"] - legs[i]["energy"]) / abs(legs[i]["energy"])
+        out["workloads"] = legs
+        out["potts2d"] = potts2d_leg(dev)
+
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(dev)
+        torch.cuda.empty_cache()
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p)
+
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def cpu_baseline(p) -> dict:

@@ -192,9 +192,10 @@ size_t pf_backward_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t 
  * the reverse step: PF_KERNEL_TWO_PASS runs two kernels (projection adjoint,
  * then label adjoint), PF_KERNEL_FUSED one fused kernel (PF_EUNSUPPORTED
  * beyond 8 Potts labels in 2-D, 4 in 3-D, or 4 leaves / 8 flows on a 2-D
- * label graph; not for 3-D label graphs), PF_KERNEL_AUTO the fused one where available; both give the same gradients bit for bit.  The tape and
- * the inputs must be those of the recorded call: the library cannot check
- * that.  Calls sharing a workspace must not overlap. */
+ * label graph; not for 3-D label graphs), PF_KERNEL_AUTO the two kernels
+ * (faster on MI355X).  Both give the same gradients bit for bit.  The tape
+ * and the inputs must be those of the recorded call: the library cannot
+ * check that.  Calls sharing a workspace must not overlap. */
 int solve_potts_backward(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
                          int32_t s_mode, const pf_params *params, const float *grad_ell,
                          float *grad_D, float *grad_S, void *stream);

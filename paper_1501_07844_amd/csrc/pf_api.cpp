@@ -527,8 +527,10 @@ int run_backward(Prob &p, const pf_params *P, const float *grad_ell, float *grad
     const bool s_scalar = p.s_mode == PF_S_NODE_SCALAR;
     float *sbar = s_scalar ? reinterpret_cast<float *>(ws + L.sbar) : grad_S;
     const size_t n_sbar = (size_t)p.g.batch * (p.s_mode == PF_S_SHARED_FIELD ? 1 : p.nn) * V;
-    const bool fused = P->kernel != PF_KERNEL_TWO_PASS && adj_fused_supported(nd, p.nl, p.nn, p.ident);
-    if (P->kernel == PF_KERNEL_FUSED && !fused)
+    // AUTO: the two-kernel reverse step, measured faster on MI355X (the
+    // fused one holds one tile per compute unit at its register count)
+    const bool fused = P->kernel == PF_KERNEL_FUSED;
+    if (fused && !adj_fused_supported(nd, p.nl, p.nn, p.ident))
         return fail(PF_EUNSUPPORTED, "fused reverse kernel unavailable for this problem");
 
     StepArgs a{};
