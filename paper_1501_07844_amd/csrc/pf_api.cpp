@@ -33,8 +33,8 @@ Layout make_layout(const pf_grid &g, int nl, int nn, int storage, bool pingpong)
     off = align256(off + sizeof(ConstBlock));
     L.partials = off;
     off = align256(off + (size_t)kPartials * 4 * sizeof(double));
-    const size_t ell_b = align256((size_t)g.batch * nl * V * s);
-    const size_t q_b = align256((size_t)g.batch * nn * g.ndim * V * s);
+    const size_t ell_b = align256((size_t)g.batch * state_fields(nl, storage) * V * s);
+    const size_t q_b = align256((size_t)g.batch * state_fields(nn, storage) * g.ndim * V * s);
     L.ell[0] = off;
     off += ell_b;
     L.q[0] = off;

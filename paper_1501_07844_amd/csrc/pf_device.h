@@ -24,19 +24,22 @@ __device__ __forceinline__ float ld(const bf16s *p, size_t i) {
 }
 __device__ __forceinline__ float ld(const f16s *p, size_t i) { return (float)p[i]; }
 
-__device__ __forceinline__ void st(float *p, size_t i, float v) { p[i] = v; }
-__device__ __forceinline__ void st(bf16s *p, size_t i, float v) {
-    // round to nearest even; NaN stays a quiet NaN
+// float -> bf16 bits, round to nearest even; NaN stays a quiet NaN
+__device__ __forceinline__ uint32_t bf16_bits(float v) {
     uint32_t u = __float_as_uint(v);
-    uint16_t r;
-    if ((u & 0x7fffffffu) > 0x7f800000u) {
-        r = uint16_t((u >> 16) | 0x40u);
-    } else {
-        u += 0x7fffu + ((u >> 16) & 1u);
-        r = uint16_t(u >> 16);
-    }
-    p[i].b = r;
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
 }
+__device__ __forceinline__ uint32_t f16_bits(float v) {
+    const f16s h = (f16s)v;
+    uint16_t r;
+    __builtin_memcpy(&r, &h, 2);
+    return r;
+}
+
+__device__ __forceinline__ void st(float *p, size_t i, float v) { p[i] = v; }
+__device__ __forceinline__ void st(bf16s *p, size_t i, float v) { p[i].b = uint16_t(bf16_bits(v)); }
 __device__ __forceinline__ void st(f16s *p, size_t i, float v) { p[i] = (f16s)v; }
 
 // Per-solve constants (node capacities, path weights) live in the workspace
@@ -81,6 +84,96 @@ __device__ __forceinline__ void sto(T *base, unsigned idx, float v) {
 }
 __device__ __forceinline__ float ldf(const float *base, unsigned idx) {
     return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + idx * 4u);
+}
+
+// ------------------------------------------------------ state layout ----
+// fp32 state: one float per field and voxel, ell [B][nl][V], q [B][nn][nd][V].
+// 16-bit state: fields packed in pairs into 32-bit words, so that every state
+// load and store is an aligned dword: ell [B][ceil(nl/2)][V] words holding
+// labels (2P, 2P+1), q [B][ceil(nn/2)][nd][V] words holding component k of
+// flows (2P, 2P+1).  The neighbour of a voxel in any axis is the same word at
+// another voxel.  The spare half of an odd count is written as 0 by every
+// store (the initialisation writes ell0 there).
+template <typename T>
+inline constexpr bool kPacked = sizeof(T) == 2;
+
+__device__ __forceinline__ float half_of(uint32_t w, int h, const bf16s *) {
+    return __uint_as_float(h ? (w & 0xffff0000u) : (w << 16));
+}
+__device__ __forceinline__ float half_of(uint32_t w, int h, const f16s *) {
+    const uint16_t r = uint16_t(h ? (w >> 16) : (w & 0xffffu));
+    f16s x;
+    __builtin_memcpy(&x, &r, 2);
+    return (float)x;
+}
+__device__ __forceinline__ uint32_t pack2(float lo, float hi, const bf16s *) {
+    return bf16_bits(lo) | (bf16_bits(hi) << 16);
+}
+__device__ __forceinline__ uint32_t pack2(float lo, float hi, const f16s *) {
+    return f16_bits(lo) | (f16_bits(hi) << 16);
+}
+
+// Label L of problem b at voxel index uv.  L past the last label reads a
+// valid field (clamped; the caller masks it), and the clamp is taken on the
+// word index for packed state, so that L = 2P and 2P + 1 load the same word
+// and the compiler merges the two loads.
+template <typename T>
+__device__ __forceinline__ float ld_ell(const void *base, int b, int nl, int L, size_t V, unsigned uv) {
+    if constexpr (kPacked<T>) {
+        const int np = (nl + 1) / 2, P = L >> 1;
+        const uint32_t *p = field<uint32_t>(base, b, np, P < np ? P : np - 1, V);
+        const uint32_t w = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(p) + uv * 4u);
+        return half_of(w, L & 1, static_cast<const T *>(nullptr));
+    } else {
+        return ldf(field<float>(base, b, nl, L < nl ? L : nl - 1, V), uv);
+    }
+}
+
+// Component k of flow A of problem b at voxel index uv (A clamped as L above).
+template <typename T, int ND>
+__device__ __forceinline__ float ld_q(const void *base, int b, int nn, int A, int k, size_t V,
+                                      unsigned uv) {
+    if constexpr (kPacked<T>) {
+        const int np = (nn + 1) / 2, P = A >> 1;
+        const uint32_t *p = field<uint32_t>(base, b, np * ND, (P < np ? P : np - 1) * ND + k, V);
+        const uint32_t w = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(p) + uv * 4u);
+        return half_of(w, A & 1, static_cast<const T *>(nullptr));
+    } else {
+        return ldf(field<float>(base, b, nn * ND, (A < nn ? A : nn - 1) * ND + k, V), uv);
+    }
+}
+
+// Labels L and L + 1 (L even) at voxel uv; nothing past nl is stored (a
+// packed word's spare half gets 0).
+template <typename T>
+__device__ __forceinline__ void st_ell2(void *base, int b, int nl, int L, size_t V, unsigned uv,
+                                        float lo, float hi) {
+    if constexpr (kPacked<T>) {
+        if (L < nl) {
+            uint32_t *p = field_w<uint32_t>(base, b, (nl + 1) / 2, L >> 1, V);
+            *reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(p) + uv * 4u) =
+                pack2(lo, L + 1 < nl ? hi : 0.f, static_cast<const T *>(nullptr));
+        }
+    } else {
+        if (L < nl) sto(field_w<float>(base, b, nl, L, V), uv, lo);
+        if (L + 1 < nl) sto(field_w<float>(base, b, nl, L + 1, V), uv, hi);
+    }
+}
+
+// Component k of flows A and A + 1 (A even) at voxel uv.
+template <typename T, int ND>
+__device__ __forceinline__ void st_q2(void *base, int b, int nn, int A, int k, size_t V,
+                                      unsigned uv, float lo, float hi) {
+    if constexpr (kPacked<T>) {
+        if (A < nn) {
+            uint32_t *p = field_w<uint32_t>(base, b, (nn + 1) / 2 * ND, (A >> 1) * ND + k, V);
+            *reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(p) + uv * 4u) =
+                pack2(lo, A + 1 < nn ? hi : 0.f, static_cast<const T *>(nullptr));
+        }
+    } else {
+        if (A < nn) sto(field_w<float>(base, b, nn * ND, A * ND + k, V), uv, lo);
+        if (A + 1 < nn) sto(field_w<float>(base, b, nn * ND, (A + 1) * ND + k, V), uv, hi);
+    }
 }
 
 struct Coord {

@@ -58,18 +58,15 @@ __device__ __forceinline__ void label_point(const StepArgs &a, int b, int x, int
     for (int L = 0; L < NLMAX; ++L) {
         const int Lc = L < a.nl ? L : a.nl - 1;
         d[L] = ldf(field<float>(a.D, b, a.nl, Lc, V), uv);
-        e[L] = ldo(field<T>(a.ell_in, b, a.nl, Lc, V), uv);
+        e[L] = ld_ell<T>(a.ell_in, b, a.nl, L, V, uv);
     }
 #pragma unroll
     for (int A = 0; A < NNMAX; ++A) {
-        const int Ac = A < a.nn ? A : a.nn - 1;
-        const T *qx = field<T>(a.q_in, b, a.nn * ND, Ac * ND, V);
-        const T *qy = field<T>(a.q_in, b, a.nn * ND, Ac * ND + 1, V);
-        qpt[A][0] = ldo(qx, uv);
-        qpt[A][1] = ldo(qy, uv);
-        if constexpr (ND == 3) qpt[A][2] = ldo(field<T>(a.q_in, b, a.nn * ND, Ac * ND + 2, V), uv);
-        qm[A][0] = ldo(qx, uv - (unsigned)m[0]);
-        qm[A][1] = ldo(qy, uv - (unsigned)m[1]);
+        qpt[A][0] = ld_q<T, ND>(a.q_in, b, a.nn, A, 0, V, uv);
+        qpt[A][1] = ld_q<T, ND>(a.q_in, b, a.nn, A, 1, V, uv);
+        if constexpr (ND == 3) qpt[A][2] = ld_q<T, ND>(a.q_in, b, a.nn, A, 2, V, uv);
+        qm[A][0] = ld_q<T, ND>(a.q_in, b, a.nn, A, 0, V, uv - (unsigned)m[0]);
+        qm[A][1] = ld_q<T, ND>(a.q_in, b, a.nn, A, 1, V, uv - (unsigned)m[1]);
         qm[A][2] = ND == 3 ? qzb[A] : 0.f;
     }
 #pragma unroll
@@ -78,11 +75,12 @@ __device__ __forceinline__ void label_point(const StepArgs &a, int b, int x, int
         add_excess<NLMAX, IDENT>(a, d, A, div_from<ND>(q0, qm[A], fwd, bwd));
     }
     entropic_step<NLMAX>(a, d, e);
+    if (store) {
 #pragma unroll
-    for (int L = 0; L < NLMAX; ++L) {
-        if (store && L < a.nl) sto(field_w<T>(a.ell_out, b, a.nl, L, V), uv, e[L]);
-        u[L] = __expf(roundtrip(e[L], static_cast<const T *>(nullptr)));
+        for (int L = 0; L < NLMAX; L += 2) st_ell2<T>(a.ell_out, b, a.nl, L, V, uv, e[L], e[L + 1]);
     }
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L) u[L] = __expf(roundtrip(e[L], static_cast<const T *>(nullptr)));
 }
 
 template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
@@ -126,10 +124,8 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
         if (ND == 3 && zs > 0) {
             const int vbelow = ((zs - 1) * a.ny + ya) * a.nx + xa;
 #pragma unroll
-            for (int A = 0; A < NNMAX; ++A) {
-                const int Ac = A < a.nn ? A : a.nn - 1;
-                qzb[A] = ldo(field<T>(a.q_in, b, a.nn * ND, Ac * ND + 2, V), (unsigned)vbelow);
-            }
+            for (int A = 0; A < NNMAX; ++A)
+                qzb[A] = ld_q<T, ND>(a.q_in, b, a.nn, A, ND - 1, V, (unsigned)vbelow);
         }
         label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xa, ya, zs, qzb, own, ua, qa);
 #pragma unroll
@@ -139,10 +135,8 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
         if (ND == 3 && zs > 0) {
             const int vbelow = ((zs - 1) * a.ny + yb) * a.nx + xb;
 #pragma unroll
-            for (int A = 0; A < NNMAX; ++A) {
-                const int Ac = A < a.nn ? A : a.nn - 1;
-                qzb[A] = ldo(field<T>(a.q_in, b, a.nn * ND, Ac * ND + 2, V), (unsigned)vbelow);
-            }
+            for (int A = 0; A < NNMAX; ++A)
+                qzb[A] = ld_q<T, ND>(a.q_in, b, a.nn, A, ND - 1, V, (unsigned)vbelow);
         }
         label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xb, yb, zs, qzb, false, ub, qb);
 #pragma unroll
@@ -188,14 +182,22 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
                 if constexpr (ND == 3) gu[L][2] = h[2] ? un[L] - ua[L] : 0.f;
             }
 #pragma unroll
-            for (int A = 0; A < NNMAX; ++A) {
+            for (int A = 0; A < NNMAX; A += 2) {
                 if (A < a.nn) {
-                    float G[3], p[ND];
-                    grad_U<ND, NLMAX, IDENT>(a, A, gu, G);
-                    flow_project<ND>(a, qa[A], G, h, sv[A], p);
+                    float p[2][ND];
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+                        for (int k = 0; k < ND; ++k) p[j][k] = 0.f;
+                        if (A + j < a.nn) {
+                            float G[3];
+                            grad_U<ND, NLMAX, IDENT>(a, A + j, gu, G);
+                            flow_project<ND>(a, qa[A + j], G, h, sv[A + j], p[j]);
+                        }
+                    }
 #pragma unroll
                     for (int k = 0; k < ND; ++k)
-                        sto(field_w<T>(a.q_out, b, a.nn * ND, A * ND + k, V), (unsigned)v, p[k]);
+                        st_q2<T, ND>(a.q_out, b, a.nn, A, k, V, (unsigned)v, p[0][k], p[1][k]);
                 }
             }
         }

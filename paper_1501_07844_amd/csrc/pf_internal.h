@@ -91,6 +91,11 @@ constexpr int kPartials = 1024;
 constexpr int kBlock = 256;
 
 size_t storage_bytes(int storage);
+// Storage elements per voxel for a group of n state fields: n for fp32,
+// n rounded up to even for the 16-bit types (packed in pairs).
+inline size_t state_fields(int n, int storage) {
+    return storage == PF_FP32 ? (size_t)n : 2 * (size_t)((n + 1) / 2);
+}
 Layout make_layout(const pf_grid &g, int nl, int nn, int storage, bool pingpong);
 
 // Launchers; return hipSuccess or the launch error.

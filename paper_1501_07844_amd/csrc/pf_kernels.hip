@@ -47,16 +47,14 @@ __device__ __forceinline__ void label_body(const StepArgs &a) {
     for (int L = 0; L < NLMAX; ++L) {
         const int Lc = L < a.nl ? L : a.nl - 1;
         d[L] = ldf(field<float>(a.D, b, a.nl, Lc, V), uv);
-        e[L] = ldo(field<T>(a.ell_in, b, a.nl, Lc, V), uv);
+        e[L] = ld_ell<T>(a.ell_in, b, a.nl, L, V, uv);
     }
 #pragma unroll
     for (int A = 0; A < NNMAX; ++A) {
-        const int Ac = A < a.nn ? A : a.nn - 1;
 #pragma unroll
         for (int k = 0; k < ND; ++k) {
-            const T *qk = field<T>(a.q_in, b, a.nn * ND, Ac * ND + k, V);
-            q0[A][k] = ldo(qk, uv);
-            qm[A][k] = ldo(qk, uv - (unsigned)m[k]);
+            q0[A][k] = ld_q<T, ND>(a.q_in, b, a.nn, A, k, V, uv);
+            qm[A][k] = ld_q<T, ND>(a.q_in, b, a.nn, A, k, V, uv - (unsigned)m[k]);
         }
     }
     // compute phase
@@ -64,8 +62,7 @@ __device__ __forceinline__ void label_body(const StepArgs &a) {
     for (int A = 0; A < NNMAX; ++A) add_excess<NLMAX, IDENT>(a, d, A, div_from<ND>(q0[A], qm[A], fwd, bwd));
     entropic_step<NLMAX>(a, d, e);
 #pragma unroll
-    for (int L = 0; L < NLMAX; ++L)
-        if (L < a.nl) sto(field_w<T>(a.ell_out, b, a.nl, L, V), uv, e[L]);
+    for (int L = 0; L < NLMAX; L += 2) st_ell2<T>(a.ell_out, b, a.nl, L, V, uv, e[L], e[L + 1]);
 }
 
 template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
@@ -91,17 +88,15 @@ __device__ __forceinline__ void flow_body(const StepArgs &a) {
     float e0[NLMAX], en[NLMAX][ND], qv[NNMAX][ND], sv[NNMAX];
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L) {
-        const int Lc = L < a.nl ? L : a.nl - 1;
-        const T *el = field<T>(a.ell_in, b, a.nl, Lc, V);
-        e0[L] = ldo(el, uv);
+        e0[L] = ld_ell<T>(a.ell_in, b, a.nl, L, V, uv);
 #pragma unroll
-        for (int k = 0; k < ND; ++k) en[L][k] = ldo(el, uv + (unsigned)off[k]);
+        for (int k = 0; k < ND; ++k) en[L][k] = ld_ell<T>(a.ell_in, b, a.nl, L, V, uv + (unsigned)off[k]);
     }
 #pragma unroll
     for (int A = 0; A < NNMAX; ++A) {
         const int Ac = A < a.nn ? A : a.nn - 1;
 #pragma unroll
-        for (int k = 0; k < ND; ++k) qv[A][k] = ldo(field<T>(a.q_in, b, a.nn * ND, Ac * ND + k, V), uv);
+        for (int k = 0; k < ND; ++k) qv[A][k] = ld_q<T, ND>(a.q_in, b, a.nn, A, k, V, uv);
         sv[A] = smooth(a, b, Ac, v);
     }
     // compute phase: labels u = exp(ell), their forward differences, the
@@ -114,13 +109,21 @@ __device__ __forceinline__ void flow_body(const StepArgs &a) {
         for (int k = 0; k < ND; ++k) gu[L][k] = h[k] ? __expf(en[L][k]) - u0 : 0.f;
     }
 #pragma unroll
-    for (int A = 0; A < NNMAX; ++A) {
+    for (int A = 0; A < NNMAX; A += 2) {
         if (A < a.nn) {
-            float G[3], p[ND];
-            grad_U<ND, NLMAX, IDENT>(a, A, gu, G);
-            flow_project<ND>(a, qv[A], G, h, sv[A], p);
+            float p[2][ND];
 #pragma unroll
-            for (int k = 0; k < ND; ++k) sto(field_w<T>(a.q_out, b, a.nn * ND, A * ND + k, V), uv, p[k]);
+            for (int j = 0; j < 2; ++j) {
+#pragma unroll
+                for (int k = 0; k < ND; ++k) p[j][k] = 0.f;
+                if (A + j < a.nn) {
+                    float G[3];
+                    grad_U<ND, NLMAX, IDENT>(a, A + j, gu, G);
+                    flow_project<ND>(a, qv[A + j], G, h, sv[A + j], p[j]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < ND; ++k) st_q2<T, ND>(a.q_out, b, a.nn, A, k, V, uv, p[0][k], p[1][k]);
         }
     }
 }
@@ -158,12 +161,11 @@ __global__ __launch_bounds__(kBlock) void k_export(StepArgs a, float *u, int32_t
     if (v >= a.V) return;
     const int b = blockIdx.y;
     const size_t V = (size_t)a.V;
-    const T *ell = static_cast<const T *>(a.ell_in);
     int best = 0;
     float bv = -INFINITY;
     for (int L = 0; L < a.nl; ++L) {
         const size_t i = ((size_t)b * a.nl + L) * V + v;
-        const float e = ld(ell, i);
+        const float e = ld_ell<T>(a.ell_in, b, a.nl, L, V, (unsigned)v);
         if (u) u[i] = expf(e);
         if (e > bv) {
             bv = e;
@@ -172,18 +174,21 @@ __global__ __launch_bounds__(kBlock) void k_export(StepArgs a, float *u, int32_t
     }
     if (labels) labels[(size_t)b * V + v] = best;
     if (qo) {
-        const T *q = static_cast<const T *>(a.q_in);
-        for (int j = 0; j < a.nn * ND; ++j) {
-            const size_t i = ((size_t)b * a.nn * ND + j) * V + v;
-            qo[i] = ld(q, i);
-        }
+        for (int A = 0; A < a.nn; ++A)
+            for (int k = 0; k < ND; ++k)
+                qo[((size_t)b * a.nn * ND + A * ND + k) * V + v] =
+                    ld_q<T, ND>(a.q_in, b, a.nn, A, k, V, (unsigned)v);
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_export_ell(const T *ell, float *out, size_t n) {
-    const size_t stride = (size_t)gridDim.x * kBlock;
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) out[i] = ld(ell, i);
+__global__ __launch_bounds__(kBlock) void k_export_ell(StepArgs a, float *out) {
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= a.V) return;
+    const int b = blockIdx.y;
+    const size_t V = (size_t)a.V;
+    for (int L = 0; L < a.nl; ++L)
+        out[((size_t)b * a.nl + L) * V + v] = ld_ell<T>(a.ell_in, b, a.nl, L, V, (unsigned)v);
 }
 
 __global__ __launch_bounds__(kBlock) void k_check(const float *D, size_t nD, const float *S,
@@ -215,8 +220,6 @@ __device__ __forceinline__ void energy_body(const StepArgs &a, double *partials)
     __shared__ double red[4][kBlock];
     const size_t V = (size_t)a.V;
     const size_t total = V * a.B;
-    const T *ell = static_cast<const T *>(a.ell_in);
-    const T *q = static_cast<const T *>(a.q_in);
     double e_sum = 0.0, p_sum = 0.0, mx_s = 0.0, mx_q = -INFINITY;
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
          i += (size_t)gridDim.x * kBlock) {
@@ -234,12 +237,13 @@ __device__ __forceinline__ void energy_body(const StepArgs &a, double *partials)
         for (int L = 0; L < NLMAX; ++L) {
             if (L < a.nl) {
                 const size_t fi = ((size_t)b * a.nl + L) * V + v;
-                u[L] = expf(ld(ell, fi));
+                u[L] = expf(ld_ell<T>(a.ell_in, b, a.nl, L, V, (unsigned)v));
                 su += (double)u[L];
                 d[L] = (double)a.D[fi];
                 e += d[L] * (double)u[L];
 #pragma unroll
-                for (int k = 0; k < ND; ++k) un[L][k] = h[k] ? expf(ld(ell, fi + off[k])) : u[L];
+                for (int k = 0; k < ND; ++k)
+                    un[L][k] = h[k] ? expf(ld_ell<T>(a.ell_in, b, a.nl, L, V, (unsigned)(v + off[k]))) : u[L];
             }
         }
 #pragma unroll
@@ -270,19 +274,20 @@ __device__ __forceinline__ void energy_body(const StepArgs &a, double *partials)
                 const double S = (double)smooth(a, b, A, v);
                 e += S * sqrt(n2);
                 // flow excess over the capacity and divergence, fp64
-                const T *qa = q + ((size_t)b * a.nn + A) * ND * V;
+                const unsigned uv = (unsigned)v;
                 double qn2 = 0.0, dv = 0.0;
-                const double qx = ld(qa, v), qy = ld(qa, V + v);
+                const double qx = ld_q<T, ND>(a.q_in, b, a.nn, A, 0, V, uv);
+                const double qy = ld_q<T, ND>(a.q_in, b, a.nn, A, 1, V, uv);
                 qn2 += qx * qx + qy * qy;
                 if (c.x < a.nx - 1) dv += qx;
-                if (c.x > 0) dv -= (double)ld(qa, v - 1);
+                if (c.x > 0) dv -= (double)ld_q<T, ND>(a.q_in, b, a.nn, A, 0, V, uv - 1u);
                 if (c.y < a.ny - 1) dv += qy;
-                if (c.y > 0) dv -= (double)ld(qa, V + v - a.nx);
+                if (c.y > 0) dv -= (double)ld_q<T, ND>(a.q_in, b, a.nn, A, 1, V, uv - (unsigned)a.nx);
                 if constexpr (ND == 3) {
-                    const double qz = ld(qa, 2 * V + v);
+                    const double qz = ld_q<T, ND>(a.q_in, b, a.nn, A, 2, V, uv);
                     qn2 += qz * qz;
                     if (c.z < a.nz - 1) dv += qz;
-                    if (c.z > 0) dv -= (double)ld(qa, 2 * V + v - off[2]);
+                    if (c.z > 0) dv -= (double)ld_q<T, ND>(a.q_in, b, a.nn, A, 2, V, uv - (unsigned)off[2]);
                 }
                 mx_q = fmax(mx_q, sqrt(qn2) - S);
                 if constexpr (IDENT) {
@@ -413,8 +418,8 @@ unsigned stride_blocks(size_t n) {
 size_t storage_bytes(int storage) { return storage == PF_FP32 ? 4 : 2; }
 
 hipError_t launch_init(const StepArgs &a, int nd, int storage, float ell0, hipStream_t s) {
-    const size_t n_ell = (size_t)a.B * a.nl * a.V;
-    const size_t n_q = (size_t)a.B * a.nn * nd * a.V;
+    const size_t n_ell = (size_t)a.B * state_fields(a.nl, storage) * a.V;
+    const size_t n_q = (size_t)a.B * state_fields(a.nn, storage) * nd * a.V;
     return dispatch_type(storage, [&]<typename T>() {
         k_init<T><<<stride_blocks(n_ell > n_q ? n_ell : n_q), kBlock, 0, s>>>(
             static_cast<T *>(a.ell_out), n_ell, static_cast<T *>(a.q_out), n_q, ell0);
@@ -423,8 +428,8 @@ hipError_t launch_init(const StepArgs &a, int nd, int storage, float ell0, hipSt
 }
 
 hipError_t launch_copy_state(const StepArgs &a, int nd, int storage, hipStream_t s) {
-    const size_t n_ell = (size_t)a.B * a.nl * a.V;
-    const size_t n_q = (size_t)a.B * a.nn * nd * a.V;
+    const size_t n_ell = (size_t)a.B * state_fields(a.nl, storage) * a.V;
+    const size_t n_q = (size_t)a.B * state_fields(a.nn, storage) * nd * a.V;
     return dispatch_type(storage, [&]<typename T>() {
         k_copy<T><<<stride_blocks(n_q), kBlock, 0, s>>>(
             static_cast<const T *>(a.ell_in), static_cast<T *>(a.ell_out), n_ell,
@@ -479,9 +484,8 @@ hipError_t launch_export(const StepArgs &a, int nd, int storage, float *u, int32
 }
 
 hipError_t launch_export_ell(const StepArgs &a, int storage, float *ell, hipStream_t s) {
-    const size_t n = (size_t)a.B * a.nl * a.V;
     return dispatch_type(storage, [&]<typename T>() {
-        k_export_ell<T><<<stride_blocks(n), kBlock, 0, s>>>(static_cast<const T *>(a.ell_in), ell, n);
+        k_export_ell<T><<<voxel_grid(a), kBlock, 0, s>>>(a, ell);
         return hipGetLastError();
     });
 }
