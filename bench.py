@@ -11,7 +11,7 @@ Prints one JSON line: voxel-label iterations per second (voxel-label = voxels
 x non-source label nodes) of the headline solve; the roofline of its
 per-iteration kernel, timed with HIP events inside the timed region; the
 per-iteration kernel rates of every workload (Potts 2-D and 3-D, HMF, DAGMF;
-float32 and bf16 state); a plain device copy as the achievable bandwidth;
+float32, bf16 and fp16 state); a plain device copy as the achievable bandwidth;
 the cost of the differentiable solve; and the float64 reference
 implementation timed on a bounded sample on the host.
 
@@ -37,8 +37,9 @@ COPY_BYTES = 1 << 30          # the copy kernel moves 1 GiB in and 1 GiB out
 
 
 def _kernel_source_hash() -> str:
+    """Hash of the sources the headline kernel is built from."""
     h = hashlib.sha256()
-    for f in ("pf_kernels.hip", "pf_fused.hip", "pf_device.h", "pf_api.cpp", "pf_internal.h"):
+    for f in ("pf_fused.hip", "pf_device.h", "pf_internal.h"):
         with open(os.path.join(ROOT, "paper_1501_07844_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -324,16 +325,18 @@ def main() -> int:
         for make, iters in ((lambda: synth.potts3d_voronoi(n=args.n), 20),
                             (synth.hmf_ellipsoids, 20), (synth.dagmf_blobs, 10)):
             q = make()
-            for storage in ("fp32", "bf16"):
+            for storage in ("fp32", "bf16", "fp16"):
                 leg = kernel_leg(q, storage, iters, dev)
                 print(f"[bench] {leg['workload']} {storage}: {leg['ms_per_iter']} ms/iter, "
                       f"{leg['alg_GBs']} GB/s alg", file=sys.stderr, flush=True)
                 legs.append(leg)
                 torch.cuda.empty_cache()
             del q
-        for i in range(0, len(legs), 2):
-            legs[i + 1]["speedup_vs_fp32"] = round(legs[i]["ms_per_iter"] / legs[i + 1]["ms_per_iter"], 3)
-            legs[i + 1]["rel_energy_vs_fp32"] = abs(legs[i + 1]["energy"] - legs[i]["energy"]) / abs(legs[i]["energy"])
+        for i in range(0, len(legs), 3):
+            for j in (1, 2):
+                legs[i + j]["speedup_vs_fp32"] = round(legs[i]["ms_per_iter"] / legs[i + j]["ms_per_iter"], 3)
+                legs[i + j]["rel_energy_vs_fp32"] = (abs(legs[i + j]["energy"] - legs[i]["energy"])
+                                                     / abs(legs[i]["energy"]))
         out["workloads"] = legs
         out["potts2d"] = potts2d_leg(dev)
 

@@ -218,16 +218,51 @@ __global__ void k_zero_flag(int32_t *flag) {
 template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
 __device__ __forceinline__ void energy_body(const StepArgs &a, double *partials) {
     __shared__ double red[4][kBlock];
+    // path weights staged in LDS once per block: read in the voxel loop
+    // without scalar-memory waits (they are 0 outside the graph)
+    __shared__ float wsh[IDENT ? 1 : NNMAX * NLMAX];
+    if constexpr (!IDENT) {
+        for (int i = threadIdx.x; i < NNMAX * NLMAX; i += kBlock)
+            wsh[i] = wgt(a, i / NLMAX, i % NLMAX);
+        __syncthreads();
+    }
     const size_t V = (size_t)a.V;
     const size_t total = V * a.B;
     double e_sum = 0.0, p_sum = 0.0, mx_s = 0.0, mx_q = -INFINITY;
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total;
          i += (size_t)gridDim.x * kBlock) {
+        // compiler-only memory barrier (no instruction): keeps the LDS weight
+        // reads inside the loop instead of hoisting all of them into registers
+        asm volatile("" ::: "memory");
         const int b = (int)(i / V);
         const int v = (int)(i - (size_t)b * V);
         const Coord c = coord_of(v, a.nx, a.ny);
         const bool h[3] = {c.x < a.nx - 1, c.y < a.ny - 1, ND == 3 && c.z < a.nz - 1};
-        const int off[3] = {1, a.nx, a.nx * a.ny};
+        const int off[3] = {h[0] ? 1 : 0, h[1] ? a.nx : 0, h[2] ? a.nx * a.ny : 0};
+        int m[3];
+        bool bwd[3];
+        backward_offsets(c, a, m, bwd);
+        const unsigned uv = (unsigned)v;
+        // load phase (unconditional, clamped indices), as in the iteration kernels
+        float e0[NLMAX], en[NLMAX][ND], dl[NLMAX], q0[NNMAX][3], qm[NNMAX][3], sv[NNMAX];
+#pragma unroll
+        for (int L = 0; L < NLMAX; ++L) {
+            e0[L] = ld_ell<T>(a.ell_in, b, a.nl, L, V, uv);
+#pragma unroll
+            for (int k = 0; k < ND; ++k) en[L][k] = ld_ell<T>(a.ell_in, b, a.nl, L, V, uv + (unsigned)off[k]);
+            dl[L] = ldf(field<float>(a.D, b, a.nl, L < a.nl ? L : a.nl - 1, V), uv);
+        }
+#pragma unroll
+        for (int A = 0; A < NNMAX; ++A) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) q0[A][k] = qm[A][k] = 0.f;
+#pragma unroll
+            for (int k = 0; k < ND; ++k) {
+                q0[A][k] = ld_q<T, ND>(a.q_in, b, a.nn, A, k, V, uv);
+                qm[A][k] = ld_q<T, ND>(a.q_in, b, a.nn, A, k, V, uv - (unsigned)m[k]);
+            }
+            sv[A] = smooth(a, b, A < a.nn ? A : a.nn - 1, v);
+        }
         // labels at x and at the forward neighbours (float32 exp of the stored
         // state), every product and sum in float64
         float u[NLMAX], un[NLMAX][ND];
@@ -235,15 +270,13 @@ __device__ __forceinline__ void energy_body(const StepArgs &a, double *partials)
         double su = 0.0, e = 0.0;
 #pragma unroll
         for (int L = 0; L < NLMAX; ++L) {
-            if (L < a.nl) {
-                const size_t fi = ((size_t)b * a.nl + L) * V + v;
-                u[L] = expf(ld_ell<T>(a.ell_in, b, a.nl, L, V, (unsigned)v));
-                su += (double)u[L];
-                d[L] = (double)a.D[fi];
-                e += d[L] * (double)u[L];
+            u[L] = expf(e0[L]);
 #pragma unroll
-                for (int k = 0; k < ND; ++k)
-                    un[L][k] = h[k] ? expf(ld_ell<T>(a.ell_in, b, a.nl, L, V, (unsigned)(v + off[k]))) : u[L];
+            for (int k = 0; k < ND; ++k) un[L][k] = h[k] ? expf(en[L][k]) : u[L];
+            d[L] = (double)dl[L];
+            if (L < a.nl) {
+                su += (double)u[L];
+                e += d[L] * (double)u[L];
             }
         }
 #pragma unroll
@@ -258,47 +291,31 @@ __device__ __forceinline__ void energy_body(const StepArgs &a, double *partials)
                 } else {
 #pragma unroll
                     for (int L = 0; L < NLMAX; ++L) {
-                        if (L < a.nl) {
-                            const double wl = (double)wgt(a, A, L);
-                            if (wl != 0.0) {
+                        const double wl = (double)wsh[A * NLMAX + L];
 #pragma unroll
-                                for (int k = 0; k < ND; ++k)
-                                    G[k] += wl * ((double)un[L][k] - (double)u[L]);
-                            }
-                        }
+                        for (int k = 0; k < ND; ++k) G[k] += wl * ((double)un[L][k] - (double)u[L]);
                     }
                 }
                 double n2 = 0.0;
 #pragma unroll
                 for (int k = 0; k < ND; ++k) n2 += G[k] * G[k];
-                const double S = (double)smooth(a, b, A, v);
+                const double S = (double)sv[A];
                 e += S * sqrt(n2);
                 // flow excess over the capacity and divergence, fp64
-                const unsigned uv = (unsigned)v;
                 double qn2 = 0.0, dv = 0.0;
-                const double qx = ld_q<T, ND>(a.q_in, b, a.nn, A, 0, V, uv);
-                const double qy = ld_q<T, ND>(a.q_in, b, a.nn, A, 1, V, uv);
-                qn2 += qx * qx + qy * qy;
-                if (c.x < a.nx - 1) dv += qx;
-                if (c.x > 0) dv -= (double)ld_q<T, ND>(a.q_in, b, a.nn, A, 0, V, uv - 1u);
-                if (c.y < a.ny - 1) dv += qy;
-                if (c.y > 0) dv -= (double)ld_q<T, ND>(a.q_in, b, a.nn, A, 1, V, uv - (unsigned)a.nx);
-                if constexpr (ND == 3) {
-                    const double qz = ld_q<T, ND>(a.q_in, b, a.nn, A, 2, V, uv);
-                    qn2 += qz * qz;
-                    if (c.z < a.nz - 1) dv += qz;
-                    if (c.z > 0) dv -= (double)ld_q<T, ND>(a.q_in, b, a.nn, A, 2, V, uv - (unsigned)off[2]);
+#pragma unroll
+                for (int k = 0; k < ND; ++k) {
+                    const double qk = q0[A][k];
+                    qn2 += qk * qk;
+                    dv += h[k] ? qk : 0.0;
+                    dv -= bwd[k] ? (double)qm[A][k] : 0.0;
                 }
                 mx_q = fmax(mx_q, sqrt(qn2) - S);
                 if constexpr (IDENT) {
                     d[A] += dv;
                 } else {
 #pragma unroll
-                    for (int L = 0; L < NLMAX; ++L)
-                        if (L < a.nl) {
-                            const double wl = (double)wgt(a, A, L);
-                            if (wl != 0.0) d[L] += wl * dv;
-                        }
+                    for (int L = 0; L < NLMAX; ++L) d[L] += (double)wsh[A * NLMAX + L] * dv;
                 }
             }
         }
