@@ -10,8 +10,10 @@ starts.
 Prints one JSON line: voxel-label iterations per second (voxel-label = voxels
 x non-source label nodes) of the headline solve; the roofline of its
 per-iteration kernel, timed with HIP events inside the timed region; the
-per-iteration kernel rates of every workload (Potts 2-D and 3-D, HMF, DAGMF;
-float32, bf16 and fp16 state); a plain device copy as the achievable bandwidth;
+per-iteration kernel rates of every workload (Potts 3-D, HMF, DAGMF and an
+Ishikawa chain scaled to 128 x 256 x 256 with 8 ordered labels; float32, bf16
+and fp16 state), whole-solve rates of the two small 2-D cases (Potts and
+Ishikawa); a plain device copy as the achievable bandwidth;
 the cost of the differentiable solve; and the float64 reference
 implementation timed on a bounded sample on the host.
 
@@ -80,6 +82,8 @@ def _solver(pf, p):
         return lambda D, S, **kw: pf.solve_potts(D, S, **kw)
     if p.kind == "hmf":
         return lambda D, S, **kw: pf.solve_hmf(D, S, p.graph, **kw)
+    if p.kind == "ishikawa":
+        return lambda D, S, **kw: pf.solve_ishikawa(D, S, **kw)
     return lambda D, S, **kw: pf.solve_dagmf(D, S, p.graph, **kw)
 
 
@@ -210,6 +214,30 @@ def potts2d_leg(dev, reps: int = 5) -> dict:
             "energy": r.energy, "gap": r.gap}
 
 
+def ishikawa2d_leg(dev, reps: int = 5) -> dict:
+    """The ordered-label workload at its own size (96 x 128, 5 levels, 200
+    iterations): whole solves per second, median of `reps`."""
+    import torch
+
+    import paper_1501_07844_amd as pf
+    from paper_1501_07844_amd import synth
+    p = synth.ishikawa_levels()
+    D, S = _inputs(p, dev)
+    kw = dict(c=p.c, tau=p.tau, iters=p.iters, s_mode=p.s_mode, ndim=2, final_energy=True)
+    r = pf.solve_ishikawa(D, S, **kw)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = pf.solve_ishikawa(D, S, workspace=r.workspace, **kw)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    t = sorted(ts)[len(ts) // 2]
+    return {"workload": "ishikawa_levels 96x128, 5 ordered labels, 200 iterations, fp32",
+            "ms_per_solve": round(1e3 * t, 3), "iterations_per_s": round(p.iters / t, 1),
+            "energy": r.energy, "gap": r.gap}
+
+
 def counters_program() -> int:
     """Short program for rocprofv3 counter passes: one copy of COPY_BYTES
     (the calibration kernel), then 5 iterations of the headline solve."""
@@ -323,7 +351,8 @@ def main() -> int:
     if not args.no_workloads:
         legs = []
         for make, iters in ((lambda: synth.potts3d_voronoi(n=args.n), 20),
-                            (synth.hmf_ellipsoids, 20), (synth.dagmf_blobs, 10)):
+                            (synth.hmf_ellipsoids, 20), (synth.dagmf_blobs, 10),
+                            (lambda: synth.ishikawa_levels(shape=(128, 256, 256), n_levels=7), 20)):
             q = make()
             for storage in ("fp32", "bf16", "fp16"):
                 leg = kernel_leg(q, storage, iters, dev)
@@ -339,6 +368,7 @@ def main() -> int:
                                                      / abs(legs[i]["energy"]))
         out["workloads"] = legs
         out["potts2d"] = potts2d_leg(dev)
+        out["ishikawa2d"] = ishikawa2d_leg(dev)
 
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(dev)

@@ -89,6 +89,27 @@ def test_state_memory_below_paper_buffer_count():
         assert fields <= paper
 
 
+def test_ishikawa_state_below_paper_buffer_count():
+    """Ishikawa chain (Algorithm 3, discussion after it): 5N + 2 buffers for N
+    levels (N + 1 labels, N flows).  The library keeps N + 1 log-labels and
+    nd components per flow (d and U live in registers): 3N + 1 in 2-D, 4N + 1
+    in 3-D.  With N = 1 the chain is the binary model, whose pseudo-flow form
+    the paper counts as 4 buffers: 2 labels + one 2-D flow."""
+    lib = pf.library()
+    golden = _golden_buffers()
+    for nd, (Z, Y, X) in ((2, (1, 256, 256)), (3, (64, 64, 64))):
+        V = Z * Y * X                     # large enough that the < 64 KB of
+        for N in (1, 2, 4, 8, 15):       # fixed workspace is under one field
+            g = _grid(1, nd, Z, Y, X)
+            p = _params(storage=0, kernel=pf.KERNEL["two_pass"])
+            n = lib.pf_workspace_bytes(C.byref(g), N + 1, N, C.byref(p))
+            fields = n // (V * 4)
+            assert fields == (N + 1) + nd * N
+            assert fields <= golden["ishikawa_per_level"] * N + golden["ishikawa_extra"]
+            if N == 1 and nd == 2:
+                assert fields == golden["binary_pseudoflow"]
+
+
 def _golden_buffers():
     path = os.path.join(ROOT, "tests", "golden", "buffer_counts.txt")
     out = {}
