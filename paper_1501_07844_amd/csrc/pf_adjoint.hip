@@ -474,7 +474,7 @@ hipError_t launch_adj_label(const StepArgs &a, const AdjArgs &g, bool ident, int
 
 hipError_t launch_adj_fused(const StepArgs &a, const AdjArgs &g, bool ident, int nd, hipStream_t s) {
     if (!adj_fused_supported(nd, a.nl, a.nn, ident)) return hipErrorInvalidValue;
-    const FusedGeom geo = tile_geometry(a, RTY);
+    const FusedGeom geo = tile_geometry(a, RTX, RTY);
     if (geo.blocks <= 0 || geo.blocks > 0x7fffffffL) return hipErrorInvalidValue;
     return adj_fused_dispatch(nd, ident, a.nl, [&]<int ND, int NL, int NN, bool ID>() {
         k_adj_fused<ND, NL, NN, ID><<<(unsigned)geo.blocks, RTHREADS, 0, s>>>(a, g, geo);

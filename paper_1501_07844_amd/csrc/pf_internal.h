@@ -107,8 +107,8 @@ hipError_t launch_fused(const StepArgs &a, bool ident, int nd, int storage, hipS
 bool fused_supported(int nd, int nl, int nn, bool identity);
 bool fused_preferred(int nd, int nl, int nn, bool identity, int storage);
 FusedGeom fused_geometry(const StepArgs &a);
-// 64-wide tiles of `rows` rows, z chunks, problems (the z-marching kernels)
-FusedGeom tile_geometry(const StepArgs &a, int rows);
+// tiles of width x rows voxels, z chunks, problems (the z-marching kernels)
+FusedGeom tile_geometry(const StepArgs &a, int width, int rows);
 hipError_t launch_copy_state(const StepArgs &a, int nd, int storage, hipStream_t s);
 hipError_t launch_energy(const StepArgs &a, bool ident, int nd, int storage,
                          double *partials, double *results, hipStream_t s);
