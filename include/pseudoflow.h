@@ -196,10 +196,10 @@ size_t pf_backward_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t 
  * (faster on MI355X).  Both give the same gradients bit for bit.  The tape
  * and the inputs must be those of the recorded call: the library cannot
  * check that.  Calls sharing a workspace must not overlap. */
-int solve_potts_backward(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
+int pf_potts_backward(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
                          int32_t s_mode, const pf_params *params, const float *grad_ell,
                          float *grad_D, float *grad_S, void *stream);
-int solve_dagmf_backward(const pf_grid *grid, const pf_graph *graph, const float *D,
+int pf_dagmf_backward(const pf_grid *grid, const pf_graph *graph, const float *D,
                          const float *S, int32_t s_mode, const pf_params *params,
                          const float *grad_ell, float *grad_D, float *grad_S, void *stream);
 

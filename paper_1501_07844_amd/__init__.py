@@ -23,7 +23,7 @@ import numpy as np
 
 __all__ = [
     "solve_potts", "solve_hmf", "solve_dagmf", "solve_ishikawa", "workspace_bytes",
-    "potts_layer", "dagmf_layer", "tape_bytes",
+    "potts_layer", "dagmf_layer", "tape_bytes", "PottsFn", "DagFn",
     "SolveResult", "PseudoflowError", "library", "lib_path", "EXPORTED",
     "PF_OK", "PF_EINVAL", "PF_EGRAPH", "PF_ENOMEM", "PF_EHIP", "PF_ENONFINITE",
     "PF_EUNSUPPORTED", "MAX_LEAVES", "MAX_NODES",
@@ -38,7 +38,7 @@ S_MODE = {"node_scalar": 0, "shared_field": 1, "node_field": 2}
 # every symbol include/pseudoflow.h declares
 EXPORTED = ["pf_workspace_bytes", "solve_potts", "solve_dagmf", "solve_hmf",
             "solve_ishikawa", "pf_last_error", "pf_abi_version", "pf_tape_bytes",
-            "pf_backward_workspace_bytes", "solve_potts_backward", "solve_dagmf_backward"]
+            "pf_backward_workspace_bytes", "pf_potts_backward", "pf_dagmf_backward"]
 ABI_VERSION = 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -118,10 +118,10 @@ def library() -> C.CDLL:
                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         bgsig = [C.POINTER(_Grid), C.POINTER(_Graph), C.c_void_p, C.c_void_p, C.c_int32,
                  C.POINTER(_Params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
-        lib.solve_potts_backward.restype = C.c_int
-        lib.solve_potts_backward.argtypes = bsig
-        lib.solve_dagmf_backward.restype = C.c_int
-        lib.solve_dagmf_backward.argtypes = bgsig
+        lib.pf_potts_backward.restype = C.c_int
+        lib.pf_potts_backward.argtypes = bsig
+        lib.pf_dagmf_backward.restype = C.c_int
+        lib.pf_dagmf_backward.argtypes = bgsig
         if lib.pf_abi_version() != ABI_VERSION:
             raise RuntimeError(f"{path}: ABI {lib.pf_abi_version()} != {ABI_VERSION}; rebuild it")
         _LIB = lib
@@ -390,13 +390,13 @@ def _autograd_fn():
             s_ptr, s_code = _s_args(Sx, spec.s_mode, grid.batch, nn, grid.nz, grid.ny, grid.nx, keep)
             stream = C.c_void_p(torch.cuda.current_stream(D.device).cuda_stream)
             if spec.kind == "potts":
-                st = lib.solve_potts_backward(C.byref(grid), nl, C.c_void_p(D.data_ptr()),
+                st = lib.pf_potts_backward(C.byref(grid), nl, C.c_void_p(D.data_ptr()),
                                               C.c_void_p(s_ptr), s_code, C.byref(p),
                                               C.c_void_p(gl.data_ptr()), C.c_void_p(gD.data_ptr()),
                                               C.c_void_p(gS.data_ptr()), stream)
             else:
                 gs = _graph_struct(spec.graph, keep)
-                st = lib.solve_dagmf_backward(C.byref(grid), C.byref(gs), C.c_void_p(D.data_ptr()),
+                st = lib.pf_dagmf_backward(C.byref(grid), C.byref(gs), C.c_void_p(D.data_ptr()),
                                               C.c_void_p(s_ptr), s_code, C.byref(p),
                                               C.c_void_p(gl.data_ptr()), C.c_void_p(gD.data_ptr()),
                                               C.c_void_p(gS.data_ptr()), stream)
@@ -436,3 +436,21 @@ def dagmf_layer(D, S, graph, *, c: float, tau: float, iters: int, ckpt_every: in
     spec = _Spec("dagmf", graph, c, tau, iters, max(1, min(ckpt_every, iters)), s_mode, nd,
                  backward_kernel)
     return _autograd_fn().apply(D, S, spec)
+
+
+class PottsFn:
+    """Function-style spelling of ``potts_layer``: ``PottsFn.apply(D, S, params)``
+    with ``params`` a dict of its keyword arguments (c, tau, iters, ...)."""
+
+    @staticmethod
+    def apply(D, S, params):
+        return potts_layer(D, S, **params)
+
+
+class DagFn:
+    """Function-style spelling of ``dagmf_layer``:
+    ``DagFn.apply(D, S, graph, params)``."""
+
+    @staticmethod
+    def apply(D, S, graph, params):
+        return dagmf_layer(D, S, graph, **params)

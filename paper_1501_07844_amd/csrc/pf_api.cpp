@@ -705,7 +705,7 @@ size_t pf_backward_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t 
     return bwd_layout(*grid, n_leaf, n_node, ckpt_every).total;
 }
 
-int solve_potts_backward(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
+int pf_potts_backward(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
                          int32_t s_mode, const pf_params *params, const float *grad_ell,
                          float *grad_D, float *grad_S, void *stream) {
     int st;
@@ -721,7 +721,7 @@ int solve_potts_backward(const pf_grid *grid, int32_t n_labels, const float *D, 
     return run_backward(p, params, grad_ell, grad_D, grad_S, static_cast<hipStream_t>(stream));
 }
 
-int solve_dagmf_backward(const pf_grid *grid, const pf_graph *graph, const float *D,
+int pf_dagmf_backward(const pf_grid *grid, const pf_graph *graph, const float *D,
                          const float *S, int32_t s_mode, const pf_params *params,
                          const float *grad_ell, float *grad_D, float *grad_S, void *stream) {
     int st;

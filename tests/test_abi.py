@@ -301,7 +301,7 @@ def test_backward_argument_errors(case, code):
         gs += 2
     elif case == "bad_params":
         p.c = 0.0
-    st = lib.solve_potts_backward(C.byref(g), 3, C.c_void_p(DEV), C.c_void_p(SADDR), 0,
+    st = lib.pf_potts_backward(C.byref(g), 3, C.c_void_p(DEV), C.c_void_p(SADDR), 0,
                                   C.byref(p), C.c_void_p(gl), C.c_void_p(gd), C.c_void_p(gs), None)
     assert st == code, (case, lib.pf_last_error())
 
@@ -313,6 +313,6 @@ def test_dag_backward_rejects_bad_graph():
     chi = (C.c_int32 * 2)(1, 0)            # cycle
     gr = pf._Graph(2, 2, par, chi, None)
     p = _params(ckpt_every=1, tape=512 * 1024, tape_bytes=1 << 30)
-    st = lib.solve_dagmf_backward(C.byref(g), C.byref(gr), C.c_void_p(DEV), C.c_void_p(SADDR), 0,
+    st = lib.pf_dagmf_backward(C.byref(g), C.byref(gr), C.c_void_p(DEV), C.c_void_p(SADDR), 0,
                                   C.byref(p), C.c_void_p(DEV), C.c_void_p(DEV), C.c_void_p(DEV), None)
     assert st == pf.PF_EGRAPH

@@ -143,10 +143,12 @@ def test_checkpoint_interval_does_not_change_gradients(name):
 
 
 def test_layer_forward_equals_plain_solve():
+    """potts_layer (through its PottsFn spelling) returns ell_K of the same
+    iteration as the plain solve."""
     p, iters, _ = CASES["potts3d_scalar"]
     D = torch.from_numpy(p.D).cuda()
-    ell = pf.potts_layer(D, torch.tensor(p.S).cuda(), c=p.c, tau=p.tau, iters=iters,
-                         s_mode=p.s_mode)
+    ell = pf.PottsFn.apply(D, torch.tensor(p.S).cuda(),
+                           dict(c=p.c, tau=p.tau, iters=iters, s_mode=p.s_mode))
     res = pf.solve_potts(D, np.asarray(p.S), c=p.c, tau=p.tau, iters=iters, kernel="two_pass",
                          s_mode=p.s_mode)
     assert float((torch.exp(ell) - res.u).abs().max()) <= 1e-6
