@@ -391,15 +391,23 @@ def cpu_baseline(p) -> dict:
     D = p.D[:, :, :nz]
     S = p.S[:, :nz]
     iters = 5
-    torch.set_num_threads(max(1, min(16, os.cpu_count() or 1)))
+    n_threads = max(1, min(16, os.cpu_count() or 1))
+    torch.set_num_threads(n_threads)
     t0 = time.perf_counter()
     O.solve_potts(D, S, p.s_mode, p.c, p.tau, iters, 3, history=False)
     dt = time.perf_counter() - t0
     V = D.shape[0] * nz * D.shape[3] * D.shape[4]
+    # the same sample for one iteration on one thread
+    torch.set_num_threads(1)
+    t1 = time.perf_counter()
+    O.solve_potts(D, S, p.s_mode, p.c, p.tau, 1, 3, history=False)
+    dt1 = time.perf_counter() - t1
+    torch.set_num_threads(n_threads)
     return {"value": V * p.n_node * iters / dt, "unit": "voxel-label-iterations/s",
-            "cores": torch.get_num_threads(), "kind": "oracle",
+            "cores": n_threads, "kind": "oracle",
             "sample": f"first {nz} z-planes ({nz}x{D.shape[3]}x{D.shape[4]}), {iters} iterations, "
-                      f"float64, {dt:.1f}s"}
+                      f"float64, {dt:.1f}s",
+            "single_thread_value": V * p.n_node / dt1}
 
 
 if __name__ == "__main__":

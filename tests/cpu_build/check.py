@@ -1,0 +1,189 @@
+"""Checks run on the threaded CPU build of the library (see run.sh): the
+library's own host code and kernel sources, compiled for the host under
+AddressSanitizer and UBSan, driven through the C ABI with host buffers.
+
+1. Forward: the fused and the two-pass iteration give the same state, energy
+   and dual bit for bit (fp32, bf16, fp16; odd label and flow counts, ragged
+   tiles, several z chunks).
+2. Reverse: recorded forward + backward against autograd through the float64
+   reference implementation, and the fused reverse step bit for bit against
+   the two-kernel one.
+
+Usage: python check.py path/to/libcpu.so
+"""
+import ctypes as C
+import os
+import sys
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+import paper_1501_07844_amd as pf                      # noqa: E402  (structs only)
+from paper_1501_07844_amd import synth                  # noqa: E402
+from oracle import pseudoflow_oracle as O               # noqa: E402
+
+lib = C.CDLL(sys.argv[1])
+for n in ("pf_tape_bytes", "pf_backward_workspace_bytes", "pf_workspace_bytes"):
+    getattr(lib, n).restype = C.c_size_t
+lib.pf_last_error.restype = C.c_char_p
+
+
+def aligned(nbytes):
+    raw = np.zeros(nbytes + 512, np.uint8)
+    return raw, raw.ctypes.data + (-raw.ctypes.data) % 256
+
+
+def ptr(a):
+    return C.c_void_p(a.ctypes.data)
+
+
+def solve(p, iters, kernel, storage, tape=None, every=0, want_ell=False):
+    B, Z, Y, X = p.shape
+    nl, nn = p.n_leaf, p.n_node
+    D = np.ascontiguousarray(p.D, np.float32)
+    S = np.ascontiguousarray(np.asarray(p.S, np.float32))
+    grid = pf._Grid(B, p.ndim, Z, Y, X)
+    keep = []
+    prm = pf._Params()
+    prm.iters, prm.c, prm.tau = iters, p.c, p.tau
+    prm.storage, prm.kernel, prm.final_energy = pf.STORAGE[storage], pf.KERNEL[kernel], 1
+    need = lib.pf_workspace_bytes(C.byref(grid), nl, nn, C.byref(prm))
+    wraw, wptr = aligned(need)
+    keep.append(wraw)
+    prm.workspace, prm.workspace_bytes = wptr, need
+    if tape is not None:
+        prm.ckpt_every, prm.tape, prm.tape_bytes = every, tape[1], tape[2]
+    u = np.zeros((B, nl, Z, Y, X), np.float32)
+    q = np.zeros((B, nn, p.ndim, Z, Y, X), np.float32)
+    ell = np.zeros_like(u)
+    r = pf._Result()
+    r.u, r.q = u.ctypes.data, q.ctypes.data
+    if want_ell:
+        r.ell = ell.ctypes.data
+    mode = pf.S_MODE[p.s_mode]
+    if p.kind == "potts":
+        st = lib.solve_potts(C.byref(grid), nl, ptr(D), ptr(S), mode, C.byref(prm), C.byref(r), None)
+    elif p.kind == "ishikawa":
+        st = lib.solve_ishikawa(C.byref(grid), nl, ptr(D), ptr(S), mode, C.byref(prm), C.byref(r), None)
+    else:
+        g = pf._graph_struct(p.graph, keep)
+        st = lib.solve_dagmf(C.byref(grid), C.byref(g), ptr(D), ptr(S), mode, C.byref(prm), C.byref(r), None)
+    if st != 0:
+        raise RuntimeError(lib.pf_last_error().decode())
+    return u, q, ell, r.energy, r.dual
+
+
+def forward_cases():
+    rng = np.random.default_rng(3)
+    dag = synth.random_dag(rng, 3, 5)
+    return [
+        ("potts3d nl3 B2 chunks", synth.random_potts(1, (40, 10, 140), 3, 3, batch=2, s_mode="node_field"), 5),
+        ("potts2d nl5 shared", synth.random_potts(2, (1, 37, 129), 2, 5, s_mode="shared_field"), 6),
+        ("potts3d nl8 scalar", synth.random_potts(3, (34, 9, 130), 3, 8, s_mode="node_scalar"), 4),
+        ("dag3d nl5 nn8 B2", synth.random_problem(4, (33, 9, 66), 3, dag, batch=2, s_mode="node_field"), 4),
+    ]
+
+
+def check_forward():
+    bad = 0
+    for name, p, iters in forward_cases():
+        for storage in ("fp32", "bf16", "fp16"):
+            a = solve(p, iters, "two_pass", storage)
+            b = solve(p, iters, "fused", storage)
+            same = all(np.array_equal(x, y) for x, y in zip(a[:2], b[:2])) and a[3:] == b[3:]
+            print(f"forward {name:24s} {storage}: fused == two-pass bitwise: {same}", flush=True)
+            bad += not same
+    return bad
+
+
+def grad(p, iters, every, bkernel, w):
+    B, Z, Y, X = p.shape
+    nl, nn = p.n_leaf, p.n_node
+    grid = pf._Grid(B, p.ndim, Z, Y, X)
+    tb = lib.pf_tape_bytes(C.byref(grid), nl, nn, iters, every)
+    traw, tptr = aligned(tb)
+    _, _, ell, _, _ = solve(p, iters, "two_pass", "fp32", tape=(traw, tptr, tb), every=every, want_ell=True)
+    D = np.ascontiguousarray(p.D, np.float32)
+    S = np.ascontiguousarray(np.asarray(p.S, np.float32))
+    gD, gS = np.full_like(D, np.nan), np.full_like(S, np.nan)
+    prm = pf._Params()
+    prm.iters, prm.c, prm.tau, prm.kernel = iters, p.c, p.tau, pf.KERNEL[bkernel]
+    bw = lib.pf_backward_workspace_bytes(C.byref(grid), nl, nn, every)
+    braw, bptr = aligned(bw)
+    prm.workspace, prm.workspace_bytes = bptr, bw
+    prm.ckpt_every, prm.tape, prm.tape_bytes = every, tptr, tb
+    gl = np.ascontiguousarray(w, np.float32)
+    args = (ptr(D), ptr(S), pf.S_MODE[p.s_mode], C.byref(prm), ptr(gl), ptr(gD), ptr(gS), None)
+    if p.kind == "potts":
+        st = lib.pf_potts_backward(C.byref(grid), nl, *args)
+    else:
+        keep = []
+        g = pf._graph_struct(p.graph, keep)
+        st = lib.pf_dagmf_backward(C.byref(grid), C.byref(g), *args)
+    if st != 0:
+        raise RuntimeError(lib.pf_last_error().decode())
+    return ell, gD, gS
+
+
+def oracle_grad(p, iters, w):
+    D = torch.tensor(p.D, dtype=torch.float64, requires_grad=True)
+    S = torch.tensor(np.asarray(p.S), dtype=torch.float64, requires_grad=True)
+    if p.kind == "potts":
+        ell = O.solve_potts(D, S, p.s_mode, p.c, p.tau, iters, p.ndim, history=False)["ell"]
+    else:
+        g = O.OracleGraph(p.graph.n_nodes, p.graph.parent, p.graph.child, p.graph.weight)
+        ell = O.solve_dagmf(D, S, p.s_mode, g, p.c, p.tau, iters, p.ndim, history=False)["ell"]
+    (ell * torch.tensor(w, dtype=torch.float64)).sum().backward()
+    return ell.detach().numpy(), D.grad.numpy(), S.grad.numpy()
+
+
+def reverse_cases():
+    rng = np.random.default_rng(7)
+    dag = synth.random_dag(rng, 3, 5)
+    tree = synth.random_tree(rng, 2, 4)
+    small = synth.random_dag(rng, 3, 4)
+    return [
+        ("potts2d nl4 shared K13 k5", synth.random_potts(11, (1, 7, 11), 2, 4, batch=2, s_mode="shared_field", c=2.0, tau=0.125), 13, 5),
+        ("potts3d nl3 scalar K9 k4", synth.random_potts(12, (4, 5, 6), 3, 3, s_mode="node_scalar", c=1.0, tau=0.125), 9, 4),
+        ("potts2d nl5 nodefield K6 k1", synth.random_potts(13, (1, 6, 9), 2, 5, s_mode="node_field", c=2.0, tau=0.125), 6, 1),
+        ("dag2d nodefield K8 k3", synth.random_problem(14, (1, 6, 7), 2, dag, batch=2, s_mode="node_field", c=4.0, tau=0.0625), 8, 3),
+        ("tree3d scalar K7 k3", synth.random_problem(15, (3, 4, 5), 3, tree, s_mode="node_scalar", c=4.0, tau=0.0625, kind="hmf"), 7, 3),
+        ("dag2d nl4 scalar K7 k3", synth.random_problem(17, (1, 19, 70), 2, small, s_mode="node_scalar", c=4.0, tau=0.0625), 7, 3),
+        ("potts3d nl3 chunks K4 k2", synth.random_potts(18, (33, 10, 67), 3, 3, s_mode="node_field", c=1.0, tau=0.125), 4, 2),
+    ]
+
+
+def fused_reverse_supported(p):
+    """The buckets the fused reverse kernel is built for (pf_adjoint.hip)."""
+    if p.ndim == 2:
+        return p.n_leaf <= 8 if p.kind == "potts" else (p.n_leaf <= 4 and p.n_node <= 8)
+    return p.kind == "potts" and p.n_leaf <= 4
+
+
+def check_reverse():
+    bad = 0
+    for name, p, iters, every in reverse_cases():
+        w = np.random.default_rng(0).standard_normal(p.D.shape).astype(np.float32)
+        ell, gD, gS = grad(p, iters, every, "two_pass", w)
+        rell, rD, rS = oracle_grad(p, iters, w)
+        eD = np.abs(gD - rD).max() / np.abs(rD).max()
+        eS = np.abs(gS - rS).max() / np.abs(rS).max()
+        ok = np.abs(ell - rell).max() < 1e-5 and eD < 1e-4 and eS < 1e-4
+        msg = f"reverse {name:28s} rel dD {eD:.1e} rel dS {eS:.1e}"
+        if fused_reverse_supported(p):
+            _, fD, fS = grad(p, iters, every, "fused", w)
+            same = np.array_equal(fD, gD) and np.array_equal(fS, gS)
+            msg += f"  fused == two-kernel bitwise: {same}"
+            ok = ok and same
+        print(msg + ("" if ok else "  BAD"), flush=True)
+        bad += not ok
+    return bad
+
+
+if __name__ == "__main__":
+    torch.set_num_threads(min(8, torch.get_num_threads()))
+    n_bad = check_forward() + check_reverse()
+    print("ALL OK" if n_bad == 0 else f"{n_bad} FAILED")
+    sys.exit(1 if n_bad else 0)

@@ -1,0 +1,45 @@
+"""Extract the kernel sections of the library sources into host-compilable
+include files for the threaded CPU build (the launch sections, which use the
+triple-chevron syntax, are left out; harness.cpp provides CPU launchers).
+
+Usage: python extract.py OUTDIR
+"""
+import os
+import shutil
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+SRC = os.path.join(ROOT, "paper_1501_07844_amd", "csrc")
+
+
+def cut(text, start_marker, end_marker):
+    i = text.index(start_marker)
+    return text[i:text.index(end_marker, i)]
+
+
+def main(out):
+    os.makedirs(out, exist_ok=True)
+    k = open(os.path.join(SRC, "pf_kernels.hip")).read()
+    k = k[:k.index("// ----------------------------------------------------------- dispatch ----")]
+    k += "\n}  // namespace\n}  // namespace pf\n"
+    f = open(os.path.join(SRC, "pf_fused.hip")).read()
+    fk = f[:f.index("template <int ND, typename T, typename F>\nhipError_t fused_bucket")]
+    fk += "\n}  // namespace\n" + cut(f, "bool fused_supported(", "hipError_t launch_fused(")
+    fk += "\n}  // namespace pf\n"
+    a = open(os.path.join(SRC, "pf_adjoint.hip")).read()
+    ak = a[:a.index("unsigned sblocks(size_t n)")] + "\n}  // namespace\n"
+    ak += cut(a, "bool adj_fused_supported(", "hipError_t launch_adj_flow(") + "\n}  // namespace pf\n"
+    # the constant address space cast has no host meaning
+    d = open(os.path.join(SRC, "pf_device.h")).read().replace(
+        "using cfloat = const __attribute__((address_space(4))) float;", "using cfloat = const float;")
+    for name, text in (("kernels.inc", k), ("fused.inc", fk), ("adjoint.inc", ak), ("pf_device.h", d)):
+        with open(os.path.join(out, name), "w") as fh:
+            fh.write(text)
+    for name in ("pf_api.cpp", "pf_internal.h"):
+        shutil.copy(os.path.join(SRC, name), os.path.join(out, name))
+    shutil.copy(os.path.join(ROOT, "include", "pseudoflow.h"), os.path.join(out, "pseudoflow.h"))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1])

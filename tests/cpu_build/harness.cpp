@@ -1,0 +1,201 @@
+// CPU launchers for the threaded build of the library's kernels: every block
+// of a launch runs in turn; kernels that synchronise (LDS exchange, block
+// reductions) run one OS thread per GPU thread with std::barrier standing in
+// for __syncthreads.  The launch geometries and template buckets mirror the
+// library's launchers.
+#include "kernels.inc"
+#include "fused.inc"
+#include "adjoint.inc"
+#include <cstdio>
+#include <cstdlib>
+#include <thread>
+#include <vector>
+thread_local dim3 blockIdx, threadIdx;
+dim3 gridDim, blockDim;
+thread_local std::barrier<> *emu_bar;
+extern "C" float __expf(float x) throw() { return expf(x); }
+extern "C" float __logf(float x) throw() { return logf(x); }
+extern "C" {
+hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, int, hipStream_t) { std::memcpy(d, s, n); return 0; }
+hipError_t hipStreamSynchronize(hipStream_t) { return 0; }
+const char *hipGetErrorString(hipError_t) { return "cpu build"; }
+}
+namespace pf {
+using namespace dev;
+template <typename F> static void run_grid(dim3 g, unsigned nt, bool threads, F f) {
+    gridDim = g;
+    blockDim = dim3(nt);
+    for (unsigned z = 0; z < g.z; ++z)
+        for (unsigned y = 0; y < g.y; ++y)
+            for (unsigned x = 0; x < g.x; ++x) {
+                if (!threads) {
+                    for (unsigned t = 0; t < nt; ++t) {
+                        blockIdx = dim3(x, y, z);
+                        threadIdx = dim3(t);
+                        emu_bar = nullptr;
+                        f();
+                    }
+                    continue;
+                }
+                std::barrier<> bar(nt);
+                std::vector<std::thread> th;
+                th.reserve(nt);
+                for (unsigned t = 0; t < nt; ++t)
+                    th.emplace_back([&, t, x, y, z] {
+                        blockIdx = dim3(x, y, z);
+                        threadIdx = dim3(t);
+                        emu_bar = &bar;
+                        f();
+                    });
+                for (auto &h : th) h.join();
+            }
+}
+static unsigned sblocks(size_t n) { size_t b = (n + 255) / 256; return (unsigned)(b < 4096 ? (b ? b : 1) : 4096); }
+static dim3 vgrid(const StepArgs &a) { return dim3((unsigned)((a.V + 255) / 256), (unsigned)a.B, 1); }
+size_t storage_bytes(int storage) { return storage == PF_FP32 ? 4 : 2; }
+template <int ND, typename T, typename F> static hipError_t bucket(bool ident, int nl, int nn, F &f) {
+    if (ident) {
+        if (nl <= 4) return f.template operator()<ND, 4, 4, true, T>();
+        if (nl <= 8) return f.template operator()<ND, 8, 8, true, T>();
+        return f.template operator()<ND, 16, 16, true, T>();
+    }
+    if (nl <= 4 && nn <= 8) return f.template operator()<ND, 4, 8, false, T>();
+    if (nl <= 8 && nn <= 16) return f.template operator()<ND, 8, 16, false, T>();
+    if (nn <= 16) return f.template operator()<ND, 16, 16, false, T>();
+    return f.template operator()<ND, 16, 32, false, T>();
+}
+template <typename F> static hipError_t disp(int nd, int st, bool ident, int nl, int nn, F &&f) {
+    if (nd == 2) {
+        if (st == PF_BF16) return bucket<2, bf16s>(ident, nl, nn, f);
+        if (st == PF_FP16) return bucket<2, f16s>(ident, nl, nn, f);
+        return bucket<2, float>(ident, nl, nn, f);
+    }
+    if (st == PF_BF16) return bucket<3, bf16s>(ident, nl, nn, f);
+    if (st == PF_FP16) return bucket<3, f16s>(ident, nl, nn, f);
+    return bucket<3, float>(ident, nl, nn, f);
+}
+template <typename F> static hipError_t dtype(int st, F &&f) {
+    if (st == PF_BF16) return f.template operator()<bf16s>();
+    if (st == PF_FP16) return f.template operator()<f16s>();
+    return f.template operator()<float>();
+}
+hipError_t launch_upload(const ConstBlock &c, float *dst, hipStream_t) {
+    run_grid(dim3((kConstFloats + 255) / 256), 256, false, [&] { k_upload(c, dst); });
+    return 0;
+}
+hipError_t launch_init(const StepArgs &a, int nd, int st, float ell0, hipStream_t) {
+    size_t ne = (size_t)a.B * state_fields(a.nl, st) * a.V, nq = (size_t)a.B * state_fields(a.nn, st) * nd * a.V;
+    return dtype(st, [&]<typename T>() {
+        run_grid(dim3(sblocks(ne > nq ? ne : nq)), 256, false, [&] { k_init<T>((T *)a.ell_out, ne, (T *)a.q_out, nq, ell0); });
+        return 0;
+    });
+}
+hipError_t launch_copy_state(const StepArgs &a, int nd, int st, hipStream_t) {
+    size_t ne = (size_t)a.B * state_fields(a.nl, st) * a.V, nq = (size_t)a.B * state_fields(a.nn, st) * nd * a.V;
+    return dtype(st, [&]<typename T>() {
+        run_grid(dim3(sblocks(nq)), 256, false, [&] {
+            k_copy<T>((const T *)a.ell_in, (T *)a.ell_out, ne, (const T *)a.q_in, (T *)a.q_out, nq);
+        });
+        return 0;
+    });
+}
+hipError_t launch_label(const StepArgs &a, bool ident, int nd, int st, hipStream_t) {
+    return disp(nd, st, ident, a.nl, a.nn, [&]<int ND, int NL, int NN, bool ID, typename T>() {
+        run_grid(vgrid(a), 256, false, [&] { k_label<ND, NL, NN, ID, T>(a); });
+        return 0;
+    });
+}
+hipError_t launch_flow(const StepArgs &a, bool ident, int nd, int st, hipStream_t) {
+    return disp(nd, st, ident, a.nl, a.nn, [&]<int ND, int NL, int NN, bool ID, typename T>() {
+        run_grid(vgrid(a), 256, false, [&] { k_flow<ND, NL, NN, ID, T>(a); });
+        return 0;
+    });
+}
+hipError_t launch_fused(const StepArgs &a, bool ident, int nd, int st, hipStream_t) {
+    const FusedGeom g = fused_geometry(a);
+    auto f = [&]<int ND, int NL, int NN, bool ID, typename T>() {
+        constexpr int NN2 = (NN > 16 ? 16 : NN);   // the fused build stops at 16 flows
+        run_grid(dim3((unsigned)g.blocks), FTHREADS, true, [&] { k_fused<ND, NL, NN2, ID, T>(a, g); });
+        return 0;
+    };
+    return disp(nd, st, ident, a.nl, a.nn, f);
+}
+hipError_t launch_energy(const StepArgs &a, bool ident, int nd, int st, double *partials, double *results,
+                         hipStream_t) {
+    // fewer blocks than the library (64, not kPartials) keep the threaded run
+    // short; the unused partials are set to the reduction's neutral values
+    hipError_t e = disp(nd, st, ident, a.nl, a.nn, [&]<int ND, int NL, int NN, bool ID, typename T>() {
+        run_grid(dim3(64), 256, true, [&] { k_energy<ND, NL, NN, ID, T>(a, partials); });
+        return 0;
+    });
+    for (int i = 64 * 4; i < kPartials * 4; ++i) partials[i] = (i % 4 == 3) ? -INFINITY : 0.0;
+    run_grid(dim3(1), 256, true, [&] { k_reduce(partials, kPartials, results); });
+    return e;
+}
+hipError_t launch_export(const StepArgs &a, int nd, int st, float *u, int32_t *labels, float *q, hipStream_t) {
+    return dtype(st, [&]<typename T>() {
+        if (nd == 2) run_grid(vgrid(a), 256, false, [&] { k_export<2, T>(a, u, labels, q); });
+        else run_grid(vgrid(a), 256, false, [&] { k_export<3, T>(a, u, labels, q); });
+        return 0;
+    });
+}
+hipError_t launch_export_ell(const StepArgs &a, int st, float *ell, hipStream_t) {
+    return dtype(st, [&]<typename T>() {
+        run_grid(vgrid(a), 256, false, [&] { k_export_ell<T>(a, ell); });
+        return 0;
+    });
+}
+hipError_t launch_check(const StepArgs &, int32_t *, hipStream_t) { std::abort(); }
+template <typename F> static hipError_t adisp(int nd, bool ident, int nl, int nn, F &&f) {
+    auto by = [&]<int ND>() -> hipError_t {
+        if (ident) {
+            if (nl <= 4) return f.template operator()<ND, 4, 4, true>();
+            if (nl <= 8) return f.template operator()<ND, 8, 8, true>();
+            return f.template operator()<ND, 16, 16, true>();
+        }
+        if (nl <= 4 && nn <= 8) return f.template operator()<ND, 4, 8, false>();
+        if (nl <= 8 && nn <= 16) return f.template operator()<ND, 8, 16, false>();
+        if (nn <= 16) return f.template operator()<ND, 16, 16, false>();
+        return f.template operator()<ND, 16, 32, false>();
+    };
+    return nd == 2 ? by.template operator()<2>() : by.template operator()<3>();
+}
+hipError_t launch_adj_flow(const StepArgs &a, const AdjArgs &g, bool ident, int nd, hipStream_t) {
+    return adisp(nd, ident, a.nl, a.nn, [&]<int ND, int NL, int NN, bool ID>() {
+        run_grid(vgrid(a), 256, false, [&] { k_adj_flow<ND, NL, NN, ID>(a, g); });
+        return 0;
+    });
+}
+hipError_t launch_adj_label(const StepArgs &a, const AdjArgs &g, bool ident, int nd, hipStream_t) {
+    return adisp(nd, ident, a.nl, a.nn, [&]<int ND, int NL, int NN, bool ID>() {
+        run_grid(vgrid(a), 256, false, [&] { k_adj_label<ND, NL, NN, ID>(a, g); });
+        return 0;
+    });
+}
+hipError_t launch_adj_fused(const StepArgs &a, const AdjArgs &g, bool ident, int nd, hipStream_t) {
+    if (!adj_fused_supported(nd, a.nl, a.nn, ident)) return 1;
+    const FusedGeom geo = tile_geometry(a, RTX, RTY);
+    auto f = [&]<int ND, int NL, int NN, bool ID>() {
+        run_grid(dim3((unsigned)geo.blocks), RTHREADS, true, [&] { k_adj_fused<ND, NL, NN, ID>(a, g, geo); });
+        return 0;
+    };
+    if (nd == 2) {
+        if (!ident) return f.template operator()<2, 4, 8, false>();
+        if (a.nl <= 4) return f.template operator()<2, 4, 4, true>();
+        return f.template operator()<2, 8, 8, true>();
+    }
+    return f.template operator()<3, 4, 4, true>();
+}
+hipError_t launch_fill(float *p, size_t n, float val, hipStream_t) {
+    if (n) run_grid(dim3(sblocks(n)), 256, false, [&] { k_fill(p, n, val); });
+    return 0;
+}
+hipError_t launch_copy_f(const float *x, float *y, size_t n, hipStream_t) {
+    if (n) run_grid(dim3(sblocks(n)), 256, false, [&] { k_copy_f(x, y, n); });
+    return 0;
+}
+hipError_t launch_sum_nodes(const float *sbar, int B, int nn, size_t V, float *out, hipStream_t) {
+    run_grid(dim3(nn), 256, true, [&] { k_sum_nodes(sbar, B, nn, V, out); });
+    return 0;
+}
+}  // namespace pf
