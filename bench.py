@@ -184,10 +184,22 @@ def adjoint_leg(dev, reps: int = 3) -> dict:
     f, r, b = med(f_ms), med(r_ms), med(b_ms)
     print(f"[bench] adjoint: forward {f:.2f} ms, recorded {r:.2f} ms, backward {b:.2f} ms",
           file=sys.stderr, flush=True)
+    # algorithmic bytes per voxel and unrolled step of the backward: the
+    # recomputed forward step (state read and written once, D and S read) and
+    # the reverse step (forward state q_k, ell_{k+1}; adjoints lbar, pbar read
+    # and written; dD and dS read and written; S read)
+    nl, nn, nd = p.n_leaf, p.n_node, p.ndim
+    s_f = 1 if p.s_mode == "shared_field" else (nn if p.s_mode == "node_field" else 0)
+    fwd_b = 8 * (nl + nd * nn) + 4 * nl + 4 * s_f
+    rev_b = 4 * ((nd * nn + nl) + 2 * (nl + nd * nn) + 2 * nl + 2 * s_f + s_f)
+    V = p.voxels
+    alg = (fwd_b + rev_b) * V * p.iters / (b * 1e-3) / 1e9
     return {"workload": f"diff_batch 16x256x256, 5 labels, {p.iters} iterations, checkpoint "
                         f"every {k}, fp32", "forward_ms": round(f, 3),
             "forward_recorded_ms": round(r, 3), "backward_ms": round(b, 3),
-            "backward_over_forward": round(b / f, 3), "total_over_forward": round((r + b) / f, 3)}
+            "backward_over_forward": round(b / f, 3), "total_over_forward": round((r + b) / f, 3),
+            "backward_alg_bytes_per_voxel_step": fwd_b + rev_b, "backward_alg_GBs": round(alg, 1),
+            "backward_hbm_frac": round(alg / HBM_PEAK_GBS, 4)}
 
 
 def potts2d_leg(dev, reps: int = 5) -> dict:
