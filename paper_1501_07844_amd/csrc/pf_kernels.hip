@@ -396,6 +396,7 @@ hipError_t by_bucket(bool ident, int nl, int nn, F &f) {
     }
     if (nl <= 4 && nn <= 8) return f.template operator()<ND, 4, 8, false, T>();
     if (nl <= 8 && nn <= 16) return f.template operator()<ND, 8, 16, false, T>();
+    if (nl <= 12 && nn <= 16) return f.template operator()<ND, 12, 16, false, T>();
     if (nn <= 16) return f.template operator()<ND, 16, 16, false, T>();
     return f.template operator()<ND, 16, 32, false, T>();
 }

@@ -61,6 +61,7 @@ template <int ND, typename T, typename F> static hipError_t bucket(bool ident, i
     }
     if (nl <= 4 && nn <= 8) return f.template operator()<ND, 4, 8, false, T>();
     if (nl <= 8 && nn <= 16) return f.template operator()<ND, 8, 16, false, T>();
+    if (nl <= 12 && nn <= 16) return f.template operator()<ND, 12, 16, false, T>();
     if (nn <= 16) return f.template operator()<ND, 16, 16, false, T>();
     return f.template operator()<ND, 16, 32, false, T>();
 }
@@ -114,8 +115,9 @@ hipError_t launch_flow(const StepArgs &a, bool ident, int nd, int st, hipStream_
 hipError_t launch_fused(const StepArgs &a, bool ident, int nd, int st, hipStream_t) {
     const FusedGeom g = fused_geometry(a);
     auto f = [&]<int ND, int NL, int NN, bool ID, typename T>() {
-        constexpr int NN2 = (NN > 16 ? 16 : NN);   // the fused build stops at 16 flows
-        run_grid(dim3((unsigned)g.blocks), FTHREADS, true, [&] { k_fused<ND, NL, NN2, ID, T>(a, g); });
+        // the fused build: (4, 8), (8, 16), (16, 16) for label graphs
+        constexpr int NL2 = (NL > 8 ? 16 : NL), NN2 = (NN > 16 ? 16 : NN);
+        run_grid(dim3((unsigned)g.blocks), FTHREADS, true, [&] { k_fused<ND, NL2, NN2, ID, T>(a, g); });
         return 0;
     };
     return disp(nd, st, ident, a.nl, a.nn, f);
