@@ -395,6 +395,8 @@ hipError_t by_bucket(bool ident, int nl, int nn, F &f) {
         return f.template operator()<ND, 16, 16, true, T>();
     }
     if (nl <= 4 && nn <= 8) return f.template operator()<ND, 4, 8, false, T>();
+    if (nl <= 8 && nn <= 8) return f.template operator()<ND, 8, 8, false, T>();
+    if (nl <= 8 && nn <= 12) return f.template operator()<ND, 8, 12, false, T>();
     if (nl <= 8 && nn <= 16) return f.template operator()<ND, 8, 16, false, T>();
     if (nl <= 12 && nn <= 16) return f.template operator()<ND, 12, 16, false, T>();
     if (nn <= 16) return f.template operator()<ND, 16, 16, false, T>();

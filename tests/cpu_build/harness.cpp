@@ -60,6 +60,8 @@ template <int ND, typename T, typename F> static hipError_t bucket(bool ident, i
         return f.template operator()<ND, 16, 16, true, T>();
     }
     if (nl <= 4 && nn <= 8) return f.template operator()<ND, 4, 8, false, T>();
+    if (nl <= 8 && nn <= 8) return f.template operator()<ND, 8, 8, false, T>();
+    if (nl <= 8 && nn <= 12) return f.template operator()<ND, 8, 12, false, T>();
     if (nl <= 8 && nn <= 16) return f.template operator()<ND, 8, 16, false, T>();
     if (nl <= 12 && nn <= 16) return f.template operator()<ND, 12, 16, false, T>();
     if (nn <= 16) return f.template operator()<ND, 16, 16, false, T>();
@@ -116,7 +118,8 @@ hipError_t launch_fused(const StepArgs &a, bool ident, int nd, int st, hipStream
     const FusedGeom g = fused_geometry(a);
     auto f = [&]<int ND, int NL, int NN, bool ID, typename T>() {
         // the fused build: (4, 8), (8, 16), (16, 16) for label graphs
-        constexpr int NL2 = (NL > 8 ? 16 : NL), NN2 = (NN > 16 ? 16 : NN);
+        constexpr int NL2 = (NL > 8 ? 16 : NL);
+        constexpr int NN2 = ID ? NN : (NL2 == 4 ? 8 : 16);
         run_grid(dim3((unsigned)g.blocks), FTHREADS, true, [&] { k_fused<ND, NL2, NN2, ID, T>(a, g); });
         return 0;
     };
