@@ -259,3 +259,58 @@ def test_full_size_sampled_one_step(kernel):
         worst_q = max(worst_q, float((q_ref - q_gpu).abs().max()))
     print(f"[full-size one-step] {kernel}: max|du| {worst_u:.2e}, max|dq| {worst_q:.2e}", flush=True)
     assert worst_u <= 1e-5 and worst_q <= 1e-5
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+@pytest.mark.parametrize("name", ["hmf", "dagmf"])
+def test_full_size_graph_sampled_one_step(name, storage):
+    """At the full HMF (128x256x256, 3 -> 8 tree) and DAGMF (256x512x512,
+    4 parents x 12 leaves) workloads, in the launch configuration the
+    benchmark times (AUTO kernel choice): the state after a few iterations,
+    advanced by one more iteration on the GPU, matches the float64 iteration
+    of Algorithm 2 applied to 5^3 patches around sampled voxels, from the
+    same stored state.  float32: within 1e-5.  bf16 state: the GPU rounds
+    its outputs to bf16 (log-labels: 2^-8 of the value), and its flow step
+    reads the new labels after that rounding: |du_L| <= u_L |ln u_L| 2^-9,
+    so |dU_A| <= (sum_L u_L |ln u_L|) 2^-9 <= ln(n_leaf) 2^-9 at a voxel and
+    the 1-Lipschitz projection moves the flow by at most
+    c tau 2 sqrt(3) ln(n_leaf) 2^-9, plus its own rounding 2^-8 |q|."""
+    p = synth.hmf_ellipsoids(iters=4) if name == "hmf" else synth.dagmf_blobs(iters=3)
+    solve = pf.solve_hmf if name == "hmf" else pf.solve_dagmf
+    D = torch.from_numpy(p.D).cuda()
+    kw = dict(c=p.c, tau=p.tau, ndim=3, s_mode=p.s_mode, storage=storage, return_q=True)
+    r0 = solve(D, p.S, p.graph, iters=p.iters, final_energy=True, **kw)
+    assert r0.max_simplex_err < (1e-5 if storage == "fp32" else 2e-2)
+    assert r0.gap >= -1e-6 * abs(r0.energy)
+    u0, q0 = r0.u, r0.q
+    r1 = solve(D, p.S, p.graph, iters=1, warm_start=True, workspace=r0.workspace,
+               final_energy=False, **kw)
+    g = O.OracleGraph(p.graph.n_nodes, p.graph.parent, p.graph.child, p.graph.weight)
+    _, Z, Y, X = p.shape
+    Sx = O.expand_S(p.S, p.s_mode, 1, g.n_node, 1, 1, 1)
+    rng = np.random.default_rng(98)
+    pts = [(int(rng.integers(0, Z)), int(rng.integers(0, Y)), int(rng.integers(0, X))) for _ in range(24)]
+    pts += [(0, 0, 0), (Z - 1, Y - 1, X - 1), (0, Y - 1, 17), (Z - 1, 5, 0)]
+    bf = storage != "fp32"
+    worst_l = worst_q = 0.0
+    for (z, y, x) in pts:
+        (z0, z1), (y0, y1), (x0, x1) = (_patch_bounds(z, Z), _patch_bounds(y, Y),
+                                        _patch_bounds(x, X))
+        sl = (slice(None), slice(None), slice(z0, z1), slice(y0, y1), slice(x0, x1))
+        ell = torch.log(u0[sl].double().cpu())
+        q = q0[:, :, :, z0:z1, y0:y1, x0:x1].double().cpu()
+        Dp = torch.tensor(p.D[sl], dtype=torch.float64)
+        ell1, q1, _ = O.dag_iteration(ell, q, Dp, Sx, g, p.c, p.tau, 3)
+        cz, cy, cx = z - z0, y - y0, x - x0
+        l_ref = ell1[0, :, cz, cy, cx]
+        l_gpu = torch.log(r1.u[0, :, z, y, x].double().cpu())
+        q_ref = q1[0, :, :, cz, cy, cx]
+        q_gpu = r1.q[0, :, :, z, y, x].double().cpu()
+        tol_l = (l_ref.abs() * 2.0 ** -8 if bf else 0.0) + 1e-5
+        tol_q = ((q_ref.abs() * 2.0 ** -8 + p.c * p.tau * 2 * 3 ** 0.5 * np.log(p.n_leaf) * 2.0 ** -9)
+                 if bf else 0.0) + 1e-5
+        worst_l = max(worst_l, float(((l_ref - l_gpu).abs() / tol_l).max()))
+        worst_q = max(worst_q, float(((q_ref - q_gpu).abs() / tol_q).max()))
+    print(f"[full-size one-step] {name} {storage}: max err / tol: ell {worst_l:.3f}, "
+          f"q {worst_q:.3f}", flush=True)
+    assert worst_l <= 1.0 and worst_q <= 1.0
