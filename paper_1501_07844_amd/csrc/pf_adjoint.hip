@@ -434,9 +434,9 @@ hipError_t adj_dispatch(int nd, bool ident, int nl, int nn, F &&f) {
     return nd == 2 ? by.template operator()<2>() : by.template operator()<3>();
 }
 
-// The fused reverse kernel keeps a point's whole adjoint state in registers
-// (twice on the halo wavefront); it is built for the buckets that fit in the
-// register budget of a 640-thread block without spilling: Potts up to 8
+// The fused reverse kernel keeps a point's whole adjoint state in registers;
+// it is built for the buckets that fit in the register budget of a
+// 640-thread block without spilling: Potts up to 8
 // labels in 2-D and 4 in 3-D, label graphs up to 4 leaves / 8 flows in 2-D.
 template <typename F>
 hipError_t adj_fused_dispatch(int nd, bool ident, int nl, F &&f) {
