@@ -250,14 +250,28 @@ def ishikawa2d_leg(dev, reps: int = 5) -> dict:
             "energy": r.energy, "gap": r.gap}
 
 
-def counters_program() -> int:
-    """Short program for rocprofv3 counter passes: one copy of COPY_BYTES
-    (the calibration kernel), then 5 iterations of the headline solve."""
+def counters_program(which: str = "potts3d") -> int:
+    """Short program for rocprofv3 counter passes.  "potts3d": one copy of
+    COPY_BYTES (the calibration kernel), then 5 iterations of the headline
+    solve.  "graphs": 3 two-pass iterations of DAGMF at 128x256x256 and of
+    Potts-3D at 128^3 (fp32)."""
     import torch
 
     import paper_1501_07844_amd as pf
     from paper_1501_07844_amd import synth
     dev = torch.device("cuda:0")
+    if which == "graphs":
+        p = synth.dagmf_blobs(shape=(128, 256, 256))
+        D = torch.from_numpy(p.D).to(dev)
+        pf.solve_dagmf(D, p.S, p.graph, c=p.c, tau=p.tau, iters=3, ndim=3, s_mode=p.s_mode,
+                       final_energy=False, return_u=False, return_labels=False)
+        q = synth.potts3d_voronoi(n=128)
+        D2, S2 = _inputs(q, dev)
+        pf.solve_potts(D2, S2, c=q.c, tau=q.tau, iters=3, ndim=3, s_mode=q.s_mode,
+                       kernel="two_pass", final_energy=False, return_u=False, return_labels=False)
+        torch.cuda.synchronize()
+        print(json.dumps({"counters_program": "graphs", "done": True}), flush=True)
+        return 0
     a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
     b = torch.empty_like(a)
     b.copy_(a)
@@ -283,14 +297,15 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-workloads", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--counters", action="store_true")
+    ap.add_argument("--counters", nargs="?", const="potts3d", default=None,
+                    choices=["potts3d", "graphs"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
               "z-slab design is not built", file=sys.stderr)
         return 2
     if args.counters:
-        return counters_program()
+        return counters_program(args.counters)
 
     import torch
 
