@@ -8,9 +8,9 @@ evaluation and the argmax export.  Inputs are resident in HBM before timing
 starts.
 
 Prints one JSON line: voxel-label iterations per second (voxel-label = voxels
-x non-source label nodes) of the headline solve; the roofline of its
-per-iteration kernel, timed with HIP events inside the timed region; the
-per-iteration kernel rates of every workload (Potts 3-D, HMF, DAGMF and an
+x non-source label nodes) of the headline solve; the roofline of its kernel
+(one launch covers two iterations with k_fused2), timed with HIP events inside
+the timed region; the per-iteration kernel rates of every workload (Potts 3-D, HMF, DAGMF and an
 Ishikawa chain scaled to 128 x 256 x 256 with 8 ordered labels; float32, bf16
 and fp16 state), whole-solve rates of the two small 2-D cases (Potts and
 Ishikawa); a plain device copy as the achievable bandwidth;
@@ -18,7 +18,7 @@ the cost of the differentiable solve; and the float64 reference
 implementation timed on a bounded sample on the host.
 
 ``--counters`` runs only a short program for rocprofv3 counter passes: a
-device copy of known size, then a few iterations of the headline kernel.
+device copy of known size, then a few launches of the headline kernel.
 """
 from __future__ import annotations
 
@@ -87,10 +87,24 @@ def _solver(pf, p):
     return lambda D, S, **kw: pf.solve_dagmf(D, S, p.graph, **kw)
 
 
+KERNEL_NAMES = {"fused2": "k_fused2", "fused": "k_fused", "two_pass": "k_label+k_flow"}
+
+
+def _kernel_choice(pf, p, storage: str, kernel: str) -> str:
+    if kernel != "auto":
+        return kernel
+    if p.kind == "ishikawa":
+        return "two_pass"
+    return pf.auto_kernel(p.shape, p.n_leaf, p.n_node, p.ndim, storage,
+                          identity=p.kind == "potts")
+
+
 def kernel_leg(p, storage: str, iters: int, dev, kernel: str = "auto") -> dict:
-    """Per-iteration kernel time of one workload: one warm-up solve, then a
-    solve with every iteration bracketed by HIP events on the solver's
-    stream; the mean over the iterations."""
+    """Kernel time of one workload: one warm-up solve, then a solve with
+    every launch bracketed by HIP events on the solver's stream; the mean
+    per iteration (a k_fused2 launch covers two).  alg_GBs: algorithmic
+    bytes of one iteration over the time per iteration; launch_alg_GBs: the
+    bytes one launch must move over its duration (the roofline figure)."""
     import paper_1501_07844_amd as pf
     D, S = _inputs(p, dev)
     solve = _solver(pf, p)
@@ -99,18 +113,21 @@ def kernel_leg(p, storage: str, iters: int, dev, kernel: str = "auto") -> dict:
     r = solve(D, S, **kw)
     r = solve(D, S, workspace=r.workspace, timing_stride=1, **kw)
     ms = r.kernel_ms / max(r.kernel_timed, 1)
-    fused = r.workspace.numel() > pf.workspace_bytes(p.shape, p.n_leaf, p.n_node, p.ndim,
-                                                     storage, "two_pass")
+    choice = _kernel_choice(pf, p, storage, kernel)
+    per_launch = 2 if choice == "fused2" else 1
     V = p.voxels
     ba = bytes_alg(p, storage)
     achieved = ba * V / (ms * 1e-3) / 1e9
+    launch = ba * V / (per_launch * ms * 1e-3) / 1e9
     out = {"workload": f"{p.name} {'x'.join(map(str, p.shape[1:]))}"
                        + (f" x{p.shape[0]}" if p.shape[0] > 1 else ""),
-           "storage": storage, "kernel": "k_fused" if fused else "k_label+k_flow",
+           "storage": storage, "kernel": KERNEL_NAMES[choice],
            "ms_per_iter": round(ms, 4), "iterations_timed": r.kernel_timed,
+           "iterations_per_launch": per_launch,
            "voxel_label_its_per_s": V * p.n_node / (ms * 1e-3),
            "alg_bytes_per_voxel": ba, "alg_GBs": round(achieved, 1),
-           "hbm_frac": round(achieved / HBM_PEAK_GBS, 4), "energy": r.energy}
+           "launch_alg_GBs": round(launch, 1),
+           "hbm_frac": round(launch / HBM_PEAK_GBS, 4), "energy": r.energy}
     del D, S, r
     return out
 
@@ -250,10 +267,11 @@ def ishikawa2d_leg(dev, reps: int = 5) -> dict:
             "energy": r.energy, "gap": r.gap}
 
 
-def counters_program(which: str = "potts3d") -> int:
+def counters_program(which: str = "potts3d", kernel: str = "auto") -> int:
     """Short program for rocprofv3 counter passes.  "potts3d": one copy of
-    COPY_BYTES (the calibration kernel), then 5 iterations of the headline
-    solve.  "graphs": 3 two-pass iterations of DAGMF at 128x256x256 and of
+    COPY_BYTES (the calibration kernel), then 6 iterations of the headline
+    solve (3 launches of k_fused2 with the AUTO choice; `kernel` overrides
+    it).  "graphs": 3 two-pass iterations of DAGMF at 128x256x256 and of
     Potts-3D at 128^3 (fp32)."""
     import torch
 
@@ -277,9 +295,9 @@ def counters_program(which: str = "potts3d") -> int:
     b.copy_(a)
     torch.cuda.synchronize()
     del a, b
-    p = synth.potts3d_voronoi(n=256, iters=5)
+    p = synth.potts3d_voronoi(n=256, iters=6)
     D, S = _inputs(p, dev)
-    r = pf.solve_potts(D, S, c=p.c, tau=p.tau, iters=5, ndim=3, s_mode=p.s_mode,
+    r = pf.solve_potts(D, S, c=p.c, tau=p.tau, iters=6, ndim=3, s_mode=p.s_mode, kernel=kernel,
                        final_energy=False, return_u=False, return_labels=False)
     torch.cuda.synchronize()
     print(json.dumps({"counters_program": "done", "iters": r.iters_done,
@@ -293,7 +311,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")
-    ap.add_argument("--kernel", default="auto", choices=["auto", "two_pass", "fused"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "two_pass", "fused", "fused2"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-workloads", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -305,7 +323,7 @@ def main() -> int:
               "z-slab design is not built", file=sys.stderr)
         return 2
     if args.counters:
-        return counters_program(args.counters)
+        return counters_program(args.counters, args.kernel)
 
     import torch
 
@@ -345,18 +363,22 @@ def main() -> int:
     print(f"[bench] fp32: {ms_per_step:.1f} ms/step, energy {res.energy:.6e}, gap {res.gap:.3e}",
           file=sys.stderr, flush=True)
 
-    fused = res.workspace.numel() > pf.workspace_bytes(p.shape, p.n_leaf, n_node, 3, "fp32",
-                                                       "two_pass")
-    kernel_name = "k_fused" if fused else "k_label+k_flow"
-    ba = bytes_alg(p, "fp32") * V                                  # per launch (iteration)
-    avg_ms = kms / max(kn, 1)
+    choice = _kernel_choice(pf, p, "fp32", args.kernel)
+    kernel_name = KERNEL_NAMES[choice]
+    per_launch = 2 if choice == "fused2" else 1                    # iterations per launch
+    # a launch reads and writes the state once whether it covers one or two
+    # iterations: algorithmic bytes per launch = bytes of one iteration
+    ba = bytes_alg(p, "fp32") * V
+    avg_ms = kms / max(kn, 1) * per_launch                         # per launch
     achieved = ba / (avg_ms * 1e-3) / 1e9
     src_hash = _kernel_source_hash()
     traffic = _traffic(kernel_name, src_hash)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kernel_name, "kernel_avg_ms": round(avg_ms, 4),
-                "kernel_launches_timed": kn, "algorithmic_bytes_per_launch": ba,
+                "iterations_per_launch": per_launch,
+                "kernel_launches_timed": kn // per_launch, "algorithmic_bytes_per_launch": ba,
+                "iteration_equivalent_GBs": round(achieved * per_launch, 1),
                 "source_hash": src_hash}
     del D, S, ws, res
 

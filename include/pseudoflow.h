@@ -67,10 +67,15 @@ typedef enum {
 } pf_s_mode;
 
 typedef enum {
-    PF_KERNEL_AUTO = 0,      /* the faster variant as measured on MI355X: fused for 3-D
-                                Potts with fp32 state, two-pass otherwise */
+    PF_KERNEL_AUTO = 0,      /* the faster variant as measured on MI355X: for 3-D Potts
+                                with fp32 state FUSED2 up to 8 labels, else FUSED;
+                                two-pass otherwise */
     PF_KERNEL_TWO_PASS = 1,  /* label pass then flow pass, state updated in place */
-    PF_KERNEL_FUSED = 2      /* one pass per iteration, state ping-ponged */
+    PF_KERNEL_FUSED = 2,     /* one pass per iteration, state ping-ponged */
+    PF_KERNEL_FUSED2 = 3     /* one pass per two iterations (3-D Potts, n_leaf <= 8;
+                                PF_EUNSUPPORTED otherwise), state ping-ponged; an
+                                iteration that ends on a gap check, or the last of an
+                                odd count, runs the one-iteration pass */
 } pf_kernel;
 
 typedef struct {
@@ -96,7 +101,9 @@ typedef struct {
     double gap_tol;          /* > 0: stop once (E - P) <= gap_tol * |E| at an evaluation */
     int32_t final_energy;    /* 1: evaluate energy, dual and gap after the last iteration */
     int32_t check_inputs;    /* 1: reject NaN/Inf in D and NaN/Inf/negative S first */
-    int32_t timing_stride;   /* > 0: time every timing_stride-th iteration with HIP events */
+    int32_t timing_stride;   /* > 0: time the launch starting every timing_stride-th
+                                iteration with HIP events (one launch covers two
+                                iterations with PF_KERNEL_FUSED2) */
     void *workspace;         /* device, 256-byte aligned, caller-owned */
     size_t workspace_bytes;
     /* Differentiable solves (float32 state only).  With tape != NULL the
@@ -123,8 +130,8 @@ typedef struct {
     double gap;              /* E - P */
     double max_simplex_err;  /* max over voxels of |sum_L u_L - 1| */
     double max_flow_excess;  /* max over flows and voxels of |q_A| - S_A (<= 0 if feasible) */
-    double kernel_ms;        /* summed duration of the timed iterations */
-    int32_t kernel_timed;    /* number of timed iterations */
+    double kernel_ms;        /* summed duration of the timed launches */
+    int32_t kernel_timed;    /* number of iterations those launches covered */
 } pf_result;
 
 /* Bytes of device workspace needed for a problem.  n_leaf end-labels and
@@ -134,6 +141,14 @@ typedef struct {
  * arguments no solver accepts. */
 size_t pf_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t n_node,
                           const pf_params *params);
+
+/* The kernel PF_KERNEL_AUTO runs for an unrecorded solve of this problem:
+ * identity != 0 for the Potts model, 0 for a label graph (the Ishikawa chain
+ * always runs PF_KERNEL_TWO_PASS); storage is a pf_storage.  Host only, no
+ * device work.  Returns PF_KERNEL_TWO_PASS, PF_KERNEL_FUSED or
+ * PF_KERNEL_FUSED2, or -1 for arguments no solver accepts. */
+int32_t pf_auto_kernel(const pf_grid *grid, int32_t n_leaf, int32_t n_node, int32_t identity,
+                       int32_t storage);
 
 /* Pseudo-flow Potts model (Algorithm 1, Potts section: relaxed Potts energy,
  * pseudo-flow dual max_{|q_L|<=S_L} sum_x min_L (D_L + div q_L), closed-form
@@ -192,7 +207,8 @@ size_t pf_backward_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t 
  * the reverse step: PF_KERNEL_TWO_PASS runs two kernels (projection adjoint,
  * then label adjoint), PF_KERNEL_FUSED one fused kernel (PF_EUNSUPPORTED
  * beyond 8 Potts labels in 2-D, 4 in 3-D, or 4 leaves / 8 flows on a 2-D
- * label graph; not for 3-D label graphs), PF_KERNEL_AUTO the two kernels
+ * label graph; not for 3-D label graphs), PF_KERNEL_FUSED2 PF_EUNSUPPORTED,
+ * PF_KERNEL_AUTO the two kernels
  * (faster on MI355X).  Both give the same gradients bit for bit.  The tape
  * and the inputs must be those of the recorded call: the library cannot
  * check that.  Calls sharing a workspace must not overlap. */

@@ -22,7 +22,7 @@ from typing import List, Optional, Sequence, Union
 import numpy as np
 
 __all__ = [
-    "solve_potts", "solve_hmf", "solve_dagmf", "solve_ishikawa", "workspace_bytes",
+    "solve_potts", "solve_hmf", "solve_dagmf", "solve_ishikawa", "workspace_bytes", "auto_kernel",
     "potts_layer", "dagmf_layer", "tape_bytes", "PottsFn", "DagFn",
     "SolveResult", "PseudoflowError", "library", "lib_path", "EXPORTED",
     "PF_OK", "PF_EINVAL", "PF_EGRAPH", "PF_ENOMEM", "PF_EHIP", "PF_ENONFINITE",
@@ -32,13 +32,14 @@ __all__ = [
 PF_OK, PF_EINVAL, PF_EGRAPH, PF_ENOMEM, PF_EHIP, PF_ENONFINITE, PF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MAX_LEAVES, MAX_NODES = 16, 32
 STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
-KERNEL = {"auto": 0, "two_pass": 1, "fused": 2}
+KERNEL = {"auto": 0, "two_pass": 1, "fused": 2, "fused2": 3}
 S_MODE = {"node_scalar": 0, "shared_field": 1, "node_field": 2}
 
 # every symbol include/pseudoflow.h declares
 EXPORTED = ["pf_workspace_bytes", "solve_potts", "solve_dagmf", "solve_hmf",
             "solve_ishikawa", "pf_last_error", "pf_abi_version", "pf_tape_bytes",
-            "pf_backward_workspace_bytes", "pf_potts_backward", "pf_dagmf_backward"]
+            "pf_backward_workspace_bytes", "pf_potts_backward", "pf_dagmf_backward",
+            "pf_auto_kernel"]
 ABI_VERSION = 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -99,6 +100,8 @@ def library() -> C.CDLL:
         lib = C.CDLL(path)
         lib.pf_workspace_bytes.restype = C.c_size_t
         lib.pf_workspace_bytes.argtypes = [C.POINTER(_Grid), C.c_int32, C.c_int32, C.POINTER(_Params)]
+        lib.pf_auto_kernel.restype = C.c_int32
+        lib.pf_auto_kernel.argtypes = [C.POINTER(_Grid), C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         sig = [C.POINTER(_Grid), C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                C.POINTER(_Params), C.POINTER(_Result), C.c_void_p]
         gsig = [C.POINTER(_Grid), C.POINTER(_Graph), C.c_void_p, C.c_void_p, C.c_int32,
@@ -178,6 +181,18 @@ def workspace_bytes(shape, n_leaf: int, n_node: int, ndim: int, storage: str = "
     p.storage = STORAGE[storage]
     p.kernel = KERNEL[kernel]
     return int(library().pf_workspace_bytes(C.byref(g), n_leaf, n_node, C.byref(p)))
+
+
+def auto_kernel(shape, n_leaf: int, n_node: int, ndim: int, storage: str = "fp32",
+                identity: bool = True) -> str:
+    """The kernel ``kernel="auto"`` runs for an unrecorded solve of a
+    [B, Z, Y, X] problem ("two_pass", "fused" or "fused2")."""
+    B, Z, Y, X = shape
+    k = int(library().pf_auto_kernel(C.byref(_Grid(B, ndim, Z, Y, X)), n_leaf, n_node,
+                                     int(bool(identity)), STORAGE[storage]))
+    if k < 0:
+        raise ValueError("no solver accepts this problem")
+    return {v: n for n, v in KERNEL.items()}[k]
 
 
 def _s_args(S, s_mode, B, nn, Z, Y, X, keep):

@@ -134,7 +134,7 @@ int check_params(const pf_params *P) {
         return fail(PF_EINVAL, "tau must be finite and > 0");
     if (P->storage < PF_FP32 || P->storage > PF_FP16)
         return fail(PF_EINVAL, "unknown storage %d", P->storage);
-    if (P->kernel < PF_KERNEL_AUTO || P->kernel > PF_KERNEL_FUSED)
+    if (P->kernel < PF_KERNEL_AUTO || P->kernel > PF_KERNEL_FUSED2)
         return fail(PF_EINVAL, "unknown kernel %d", P->kernel);
     if (P->gap_every < 0) return fail(PF_EINVAL, "gap_every must be >= 0");
     if (!(P->gap_tol >= 0.0)) return fail(PF_EINVAL, "gap_tol must be >= 0");
@@ -270,13 +270,18 @@ int check_tape(const Prob &p, const pf_params *P) {
 int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
     int tst = check_tape(p, P);
     if (tst != PF_OK) return tst;
-    if (P->tape && P->kernel == PF_KERNEL_FUSED)
+    if (P->tape && (P->kernel == PF_KERNEL_FUSED || P->kernel == PF_KERNEL_FUSED2))
         return fail(PF_EUNSUPPORTED, "a recorded solve uses the two-pass kernels");
-    const bool want_fused = !P->tape && (P->kernel == PF_KERNEL_FUSED ||
+    const bool want_fused2 = !P->tape && (P->kernel == PF_KERNEL_FUSED2 ||
+                             (P->kernel == PF_KERNEL_AUTO &&
+                              fused2_preferred(p.g.ndim, p.nl, p.nn, p.ident, P->storage)));
+    const bool want_fused = want_fused2 || (!P->tape && (P->kernel == PF_KERNEL_FUSED ||
                             (P->kernel == PF_KERNEL_AUTO &&
-                             fused_preferred(p.g.ndim, p.nl, p.nn, p.ident, P->storage)));
+                             fused_preferred(p.g.ndim, p.nl, p.nn, p.ident, P->storage))));
     if (P->kernel == PF_KERNEL_FUSED && !fused_supported(p.g.ndim, p.nl, p.nn, p.ident))
         return fail(PF_EUNSUPPORTED, "fused kernel unavailable for this problem");
+    if (want_fused2 && !fused2_supported(p.g.ndim, p.nl, p.nn, p.ident))
+        return fail(PF_EUNSUPPORTED, "two-iteration kernel unavailable for this problem");
     const Layout lay = make_layout(p.g, p.nl, p.nn, P->storage, want_fused);
     if (P->workspace_bytes < lay.total)
         return fail(PF_ENOMEM, "workspace of %zu bytes < %zu needed", P->workspace_bytes, lay.total);
@@ -368,7 +373,12 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
     int cur = 0;
     const TapeGeom tg = tape_geom(p.g, p.nl, p.nn, P->iters, P->ckpt_every);
     const size_t n_ell = (size_t)a.B * a.nl * a.V, n_q = (size_t)a.B * a.nn * nd * a.V;
-    for (int it = 0; it < P->iters; ++it) {
+    int timed_iters = 0;
+    for (int it = 0; it < P->iters;) {
+        // two iterations in one pass unless a gap check falls after the first
+        const bool pair = want_fused2 && it + 1 < P->iters &&
+                          !(P->gap_every > 0 && (it + 1) % P->gap_every == 0);
+        const int step = pair ? 2 : 1;
         if (P->tape && it % P->ckpt_every == 0) {
             char *slot = static_cast<char *>(P->tape) + (size_t)(it / P->ckpt_every) * tg.slot_bytes;
             if ((e = launch_copy_f(static_cast<const float *>(ell[0]), reinterpret_cast<float *>(slot),
@@ -391,8 +401,12 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
             a.q_in = q[cur];
             a.ell_out = ell[1 - cur];
             a.q_out = q[1 - cur];
-            if ((e = launch_fused(a, ident, nd, P->storage, stream)) != hipSuccess)
+            if (pair) {
+                if ((e = launch_fused2(a, P->storage, stream)) != hipSuccess)
+                    return hip_fail(e, "two-iteration step");
+            } else if ((e = launch_fused(a, ident, nd, P->storage, stream)) != hipSuccess) {
                 return hip_fail(e, "fused step");
+            }
             cur = 1 - cur;
             a.ell_in = a.ell_out;
             a.q_in = a.q_out;
@@ -402,9 +416,13 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
             if ((e = launch_flow(a, ident, nd, P->storage, stream)) != hipSuccess)
                 return hip_fail(e, "flow pass");
         }
-        if (timed) hipEventRecord(timer.ev.back(), stream);
-        R->iters_done = it + 1;
-        if (P->gap_every > 0 && (it + 1) % P->gap_every == 0) {
+        if (timed) {
+            hipEventRecord(timer.ev.back(), stream);
+            timed_iters += step;
+        }
+        it += step;
+        R->iters_done = it;
+        if (P->gap_every > 0 && it % P->gap_every == 0) {
             double r[4];
             const int st = evaluate(r);
             if (st != PF_OK) return st;
@@ -459,7 +477,7 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
             ms += t;
         }
         R->kernel_ms = ms;
-        R->kernel_timed = (int)(timer.ev.size() / 2);
+        R->kernel_timed = timed_iters;
     }
     g_err.clear();
     return PF_OK;
@@ -529,6 +547,8 @@ int run_backward(Prob &p, const pf_params *P, const float *grad_ell, float *grad
     const size_t n_sbar = (size_t)p.g.batch * (p.s_mode == PF_S_SHARED_FIELD ? 1 : p.nn) * V;
     // AUTO: the two-kernel reverse step, measured faster on MI355X (the
     // fused one holds one tile per compute unit at its register count)
+    if (P->kernel == PF_KERNEL_FUSED2)
+        return fail(PF_EUNSUPPORTED, "no two-iteration reverse kernel");
     const bool fused = P->kernel == PF_KERNEL_FUSED;
     if (fused && !adj_fused_supported(nd, p.nl, p.nn, p.ident))
         return fail(PF_EUNSUPPORTED, "fused reverse kernel unavailable for this problem");
@@ -645,11 +665,24 @@ size_t pf_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t n_node,
     if (n_leaf < 1 || n_leaf > PF_MAX_LEAVES || n_node < 1 || n_node > PF_MAX_NODES) return 0;
     if (params->storage < PF_FP32 || params->storage > PF_FP16) return 0;
     // the same sizes serve the identity (Potts) and weighted families
-    const bool fused = params->kernel == PF_KERNEL_FUSED ||
+    const bool fused = params->kernel == PF_KERNEL_FUSED || params->kernel == PF_KERNEL_FUSED2 ||
                        (params->kernel == PF_KERNEL_AUTO &&
                         (fused_preferred(grid->ndim, n_leaf, n_node, true, params->storage) ||
-                         fused_preferred(grid->ndim, n_leaf, n_node, false, params->storage)));
+                         fused_preferred(grid->ndim, n_leaf, n_node, false, params->storage) ||
+                         fused2_preferred(grid->ndim, n_leaf, n_node, true, params->storage)));
     return make_layout(*grid, n_leaf, n_node, params->storage, fused).total;
+}
+
+int32_t pf_auto_kernel(const pf_grid *grid, int32_t n_leaf, int32_t n_node, int32_t identity,
+                       int32_t storage) {
+    if (check_grid(grid) != PF_OK) return -1;
+    if (n_leaf < 1 || n_leaf > PF_MAX_LEAVES || n_node < 1 || n_node > PF_MAX_NODES) return -1;
+    if (storage < PF_FP32 || storage > PF_FP16) return -1;
+    const bool id = identity != 0;
+    if (id && n_node != n_leaf) return -1;
+    if (fused2_preferred(grid->ndim, n_leaf, n_node, id, storage)) return PF_KERNEL_FUSED2;
+    if (fused_preferred(grid->ndim, n_leaf, n_node, id, storage)) return PF_KERNEL_FUSED;
+    return PF_KERNEL_TWO_PASS;
 }
 
 int solve_potts(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
@@ -741,7 +774,7 @@ int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const 
     if ((st = check_params(params)) != PF_OK) return st;
     if (n_labels < 2) return fail(PF_EINVAL, "the Ishikawa chain needs n_labels >= 2");
     if (n_labels > PF_MAX_LEAVES) return fail(PF_EUNSUPPORTED, "n_labels > %d", PF_MAX_LEAVES);
-    if (params->kernel == PF_KERNEL_FUSED)
+    if (params->kernel == PF_KERNEL_FUSED || params->kernel == PF_KERNEL_FUSED2)
         return fail(PF_EUNSUPPORTED, "no fused kernel for the Ishikawa chain");
     Prob p;
     p.g = *grid;

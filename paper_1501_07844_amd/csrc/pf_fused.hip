@@ -40,14 +40,16 @@ constexpr int FTY = 4;                // owned rows per tile
 constexpr int FTHREADS = FTX * (FTY + 2);   // owned rows + the halo row + the halo column
 
 // Label step at voxel (x, y, z) of problem b.  qzb holds the old q_z of every
-// flow one plane below (ignored at z == 0).  Returns the new labels as the
-// exponential of the stored-precision log-label (what the two-pass flow
-// kernel reads back), the old flows at the voxel in qpt, and stores the new
+// flow one plane below (ignored at z == 0).  Returns the new log-labels as
+// stored (er: after the round trip through the storage type, what a later
+// load returns), the new labels u = exp(er) (what the two-pass flow kernel
+// reads back), the old flows at the voxel in qpt, and stores the new
 // log-labels when `store`.  All loads are issued first, unconditionally.
 template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
 __device__ __forceinline__ void label_point(const StepArgs &a, int b, int x, int y, int z,
                                             const float (&qzb)[NNMAX], bool store,
-                                            float (&u)[NLMAX], float (&qpt)[NNMAX][ND]) {
+                                            float (&u)[NLMAX], float (&qpt)[NNMAX][ND],
+                                            float (&er)[NLMAX]) {
     const size_t V = (size_t)a.V;
     const int v = (z * a.ny + y) * a.nx + x;
     const unsigned uv = (unsigned)v;
@@ -83,7 +85,10 @@ __device__ __forceinline__ void label_point(const StepArgs &a, int b, int x, int
         for (int L = 0; L < NLMAX; L += 2) st_ell2<T>(a.ell_out, b, a.nl, L, V, uv, e[L], e[L + 1]);
     }
 #pragma unroll
-    for (int L = 0; L < NLMAX; ++L) u[L] = __expf(roundtrip(e[L], static_cast<const T *>(nullptr)));
+    for (int L = 0; L < NLMAX; ++L) {
+        er[L] = roundtrip(e[L], static_cast<const T *>(nullptr));
+        u[L] = __expf(er[L]);
+    }
 }
 
 template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
@@ -116,7 +121,7 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
 
     const size_t V = (size_t)a.V;
 
-    float ua[NLMAX], ub[NLMAX];
+    float ua[NLMAX], ub[NLMAX], er[NLMAX];   // er: unused here
     float qa[NNMAX][ND], qb[NNMAX][ND];
     float qzb[NNMAX];
 #pragma unroll
@@ -130,7 +135,7 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
             for (int A = 0; A < NNMAX; ++A)
                 qzb[A] = ld_q<T, ND>(a.q_in, b, a.nn, A, ND - 1, V, (unsigned)vbelow);
         }
-        label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xa, ya, zs, qzb, own, ua, qa);
+        label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xa, ya, zs, qzb, own, ua, qa, er);
 #pragma unroll
         for (int L = 0; L < NLMAX; ++L) lds[L][row][col] = ua[L];
     }
@@ -141,7 +146,7 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
             for (int A = 0; A < NNMAX; ++A)
                 qzb[A] = ld_q<T, ND>(a.q_in, b, a.nn, A, ND - 1, V, (unsigned)vbelow);
         }
-        label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xb, yb, zs, qzb, false, ub, qb);
+        label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xb, yb, zs, qzb, false, ub, qb, er);
 #pragma unroll
         for (int L = 0; L < NLMAX; ++L) lds[L][col][FTX] = ub[L];
     }
@@ -165,13 +170,13 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
 #pragma unroll
             for (int A = 0; A < NNMAX; ++A) qz[A] = qa[A][ND - 1];
             label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xa, ya, z + 1, qz, own && z + 1 < ze,
-                                                    un, qn);
+                                                    un, qn, er);
         }
         if (vb && has_next) {
             float qz[NNMAX];
 #pragma unroll
             for (int A = 0; A < NNMAX; ++A) qz[A] = qb[A][ND - 1];
-            label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xb, yb, z + 1, qz, false, ubn, qb);
+            label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xb, yb, z + 1, qz, false, ubn, qb, er);
         }
         // flow step of the owned voxels of plane z
         if (own) {
@@ -226,6 +231,232 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
     }
 }
 
+// ------------------------------------------------ two iterations per pass ----
+// Temporal blocking for 3-D Potts: iterations k -> k+1 -> k+2 in one z-march,
+// so that the state is read and written once per two iterations.  The
+// dependency cone of the owned tile [x0, x0+TW) x [y0, y0+TH) widens by one
+// voxel per step in x and y:
+//   second flow step   on the owned tile           (stage D)
+//   second label step  on [x0, x0+TW] x [y0, y0+TH]   (forward neighbours, C)
+//   first flow step    on [x0-1, x0+TW] x [y0-1, y0+TH] (backward neighbours
+//                      of the divergence, B)
+//   first label step   on [x0-1, x0+TW+1] x [y0-1, y0+TH+1]   (A)
+// One thread per column of the widest region (RW x RH); along z the stages
+// lag, so that at step z the block computes A on plane z+2, B and C on plane
+// z+1 and D on plane z.  Per column a thread carries in registers the old
+// flows of plane z+1 (for B, and as the z-neighbour of A), the first
+// iteration's log-labels of plane z+1 (for C) and its flows of plane z (for
+// D, and as the z-neighbour of C); the x/y neighbours go through LDS (the
+// first iteration's labels for B, its x/y flow components for C, the second
+// iteration's labels for D).  Intermediate values are rounded to the storage
+// type exactly where the single-iteration kernels store and reload them, and
+// every point uses the same expressions, so the result equals two fused (or
+// two-pass) iterations bit for bit.
+constexpr int TW = 64;                        // owned tile width
+constexpr int TH = 8;                         // owned tile rows
+constexpr int RW = TW + 3;                    // first label step's columns
+constexpr int RH = TH + 3;                    // and rows
+constexpr int T2THREADS = (RW * RH + 63) / 64 * 64;
+
+template <int NL, typename T>
+__global__ __launch_bounds__(T2THREADS) void k_fused2(StepArgs a, FusedGeom g) {
+    constexpr int NN = NL;   // Potts: one flow per label
+    __shared__ float lu1[NL][RH][RW];      // first-iteration labels, plane z+1
+    __shared__ float lu2[NL][RH][RW];      // second-iteration labels, plane z
+    __shared__ float lq1[NN][2][RH][RW];   // first-iteration q_x, q_y, plane z+1
+    const int tid = threadIdx.x;
+    const int r = tid / RW, c = tid % RW;
+
+    // XCD-aware block -> tile mapping (as in k_fused)
+    const int nb = gridDim.x;
+    const int pb = blockIdx.x;
+    const int lb = (nb % 8 == 0) ? (pb % 8) * (nb / 8) + pb / 8 : pb;
+    const int bx = lb % g.tiles_x;
+    int rr = lb / g.tiles_x;
+    const int by = rr % g.tiles_y;
+    rr /= g.tiles_y;
+    const int ch = rr % g.n_chunks;
+    const int b = rr / g.n_chunks;
+    const int zs = ch * g.cz;
+    const int ze = min(a.nz, zs + g.cz);
+
+    const int x = bx * TW - 1 + c, y = by * TH - 1 + r;
+    const bool inA = r < RH && x >= 0 && x < a.nx && y >= 0 && y < a.ny;
+    const bool inB = inA && c <= TW + 1 && r <= TH + 1;
+    const bool inC = inB && c >= 1 && r >= 1;
+    const bool own = inC && c <= TW && r <= TH;
+    const size_t V = (size_t)a.V;
+    const float *Tn = nullptr;
+    auto vox = [&](int p) { return (unsigned)((p * a.ny + y) * a.nx + x); };
+
+    // carried: old flows of plane z+1, first-iteration log-labels of plane
+    // z+1 and flows of plane z, data term of plane z+1, capacities of plane z
+    float q0c[NN][3], e1c[NL], q1c[NN][3], dc[NL], sc[NN];
+#pragma unroll
+    for (int A = 0; A < NN; ++A) {
+        e1c[A] = dc[A] = sc[A] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) q0c[A][k] = q1c[A][k] = 0.f;
+    }
+    // first label step on plane zs - 1 (the first flow step there feeds the
+    // z-neighbour of the second label step on plane zs)
+    if (zs >= 1 && inA) {
+        float qzb[NN], u[NL], er[NL];
+#pragma unroll
+        for (int A = 0; A < NN; ++A)
+            qzb[A] = zs >= 2 ? ld_q<T, 3>(a.q_in, b, a.nn, A, 2, V, vox(zs - 2)) : 0.f;
+        label_point<3, NL, NN, true, T>(a, b, x, y, zs - 1, qzb, false, u, q0c, er);
+#pragma unroll
+        for (int L = 0; L < NL; ++L) lu1[L][r][c] = u[L];
+    }
+    __syncthreads();
+
+    for (int z = zs - 2; z < ze; ++z) {
+        const int pA = z + 2, pB = z + 1;
+        const bool doA = inA && pA < a.nz;
+        const bool doB = inB && pB >= 0 && pB >= zs - 1 && pB < a.nz;
+        const bool doC = inC && pB >= zs && pB < a.nz;
+        const bool doD = own && z >= zs;
+
+        // all global loads of the step are issued here: the first label
+        // step's inputs (its data term is kept for the second label step one
+        // step later) and the capacities of plane z + 1 (kept for the second
+        // flow step one step later)
+        float e1n[NL], u1n[NL], q0n[NN][3], dn[NL], sn[NN];
+#pragma unroll
+        for (int A = 0; A < NN; ++A) {
+            e1n[A] = u1n[A] = dn[A] = sn[A] = 0.f;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) q0n[A][k] = 0.f;
+        }
+        if (doB) {
+#pragma unroll
+            for (int A = 0; A < NN; ++A) sn[A] = smooth(a, b, A < a.nn ? A : a.nn - 1, (int)vox(pB));
+        }
+        // A: first label step, plane z + 2
+        if (doA) {
+#pragma unroll
+            for (int L = 0; L < NL; ++L)
+                dn[L] = ldf(field<float>(a.D, b, a.nl, L < a.nl ? L : a.nl - 1, V), vox(pA));
+            float qzb[NN];
+#pragma unroll
+            for (int A = 0; A < NN; ++A) qzb[A] = q0c[A][2];
+            label_point<3, NL, NN, true, T>(a, b, x, y, pA, qzb, false, u1n, q0n, e1n);
+        }
+
+        // B: first flow step, plane z + 1
+        float q1n[NN][3];
+#pragma unroll
+        for (int A = 0; A < NN; ++A)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) q1n[A][k] = 0.f;
+        if (doB) {
+            const bool h[3] = {x < a.nx - 1, y < a.ny - 1, pB + 1 < a.nz};
+#pragma unroll
+            for (int A = 0; A < NN; ++A) {
+                if (A < a.nn) {
+                    const float uo = lu1[A][r][c];
+                    float gu[NL][3];
+                    gu[A][0] = h[0] ? lu1[A][r][c + 1] - uo : 0.f;
+                    gu[A][1] = h[1] ? lu1[A][r + 1][c] - uo : 0.f;
+                    gu[A][2] = h[2] ? u1n[A] - uo : 0.f;
+                    float G[3], p[3];
+                    grad_U<3, NL, true>(a, A, gu, G);
+                    flow_project<3>(a, q0c[A], G, h, sn[A], p);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) q1n[A][k] = roundtrip(p[k], (const T *)Tn);
+                }
+                lq1[A][0][r][c] = q1n[A][0];
+                lq1[A][1][r][c] = q1n[A][1];
+            }
+        }
+        __syncthreads();   // B's reads of lu1 are done, lq1 is written
+        if (doA) {
+#pragma unroll
+            for (int L = 0; L < NL; ++L) lu1[L][r][c] = u1n[L];
+        }
+
+        // C: second label step, plane z + 1
+        float u2n[NL];
+#pragma unroll
+        for (int L = 0; L < NL; ++L) u2n[L] = 0.f;
+        if (doC) {
+            const unsigned uv = vox(pB);
+            const Coord cc{x, y, pB};
+            int m[3];
+            bool bwd[3];
+            backward_offsets(cc, a, m, bwd);
+            const bool fwd[3] = {x < a.nx - 1, y < a.ny - 1, pB < a.nz - 1};
+            float d[NL], e[NL];
+#pragma unroll
+            for (int L = 0; L < NL; ++L) {
+                d[L] = dc[L];
+                e[L] = e1c[L];
+            }
+#pragma unroll
+            for (int A = 0; A < NN; ++A) {
+                const float q0[3] = {q1n[A][0], q1n[A][1], q1n[A][2]};
+                const float qm[3] = {lq1[A][0][r][c - 1], lq1[A][1][r - 1][c], q1c[A][2]};
+                add_excess<NL, true>(a, d, A, div_from<3>(q0, qm, fwd, bwd));
+            }
+            entropic_step<NL>(a, d, e);
+            if (own && pB < ze) {
+#pragma unroll
+                for (int L = 0; L < NL; L += 2) st_ell2<T>(a.ell_out, b, a.nl, L, V, uv, e[L], e[L + 1]);
+            }
+#pragma unroll
+            for (int L = 0; L < NL; ++L) u2n[L] = __expf(roundtrip(e[L], (const T *)Tn));
+        }
+
+        // D: second flow step, plane z (owned voxels)
+        if (doD) {
+            const unsigned v = vox(z);
+            const bool h[3] = {x < a.nx - 1, y < a.ny - 1, z + 1 < a.nz};
+#pragma unroll
+            for (int A = 0; A < NN; A += 2) {
+                if (A < a.nn) {
+                    float p[2][3];
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const int Aj = A + j;
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) p[j][k] = 0.f;
+                        if (Aj < a.nn) {
+                            const float uo = lu2[Aj][r][c];
+                            float gu[NL][3];
+                            gu[Aj][0] = h[0] ? lu2[Aj][r][c + 1] - uo : 0.f;
+                            gu[Aj][1] = h[1] ? lu2[Aj][r + 1][c] - uo : 0.f;
+                            gu[Aj][2] = h[2] ? u2n[Aj] - uo : 0.f;
+                            float G[3];
+                            grad_U<3, NL, true>(a, Aj, gu, G);
+                            flow_project<3>(a, q1c[Aj], G, h, sc[Aj], p[j]);
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+                        st_q2<T, 3>(a.q_out, b, a.nn, A, k, V, v, p[0][k], p[1][k]);
+                }
+            }
+        }
+        __syncthreads();   // C's reads of lq1 and D's reads of lu2 are done
+        if (doC) {
+#pragma unroll
+            for (int L = 0; L < NL; ++L) lu2[L][r][c] = u2n[L];
+        }
+#pragma unroll
+        for (int A = 0; A < NN; ++A) {
+            e1c[A] = e1n[A];
+            dc[A] = dn[A];
+            sc[A] = sn[A];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                q0c[A][k] = q0n[A][k];
+                q1c[A][k] = q1n[A][k];
+            }
+        }
+    }
+}
+
 template <int ND, typename T, typename F>
 hipError_t fused_bucket(bool ident, int nl, int nn, F &f) {
     if (ident) {
@@ -259,23 +490,39 @@ bool fused_supported(int nd, int nl, int nn, bool identity) {
 }
 
 // PF_KERNEL_AUTO: the fused single pass where it measured faster than the
-// two-pass kernels on MI355X (3-D Potts with float32 state); the two-pass
-// kernels elsewhere (their lower register pressure wins for 16-bit state and
-// for label graphs).
+// two-pass kernels on MI355X (3-D Potts with float32 state; up to 8 labels
+// the two-iteration pass below is faster still); the two-pass kernels
+// elsewhere (their lower register pressure wins for 16-bit state and for
+// label graphs).
 bool fused_preferred(int nd, int nl, int nn, bool identity, int storage) {
     return identity && nd == 3 && storage == PF_FP32 && fused_supported(nd, nl, nn, identity);
 }
 
 FusedGeom fused_geometry(const StepArgs &a) { return tile_geometry(a, FTX, FTY); }
 
-FusedGeom tile_geometry(const StepArgs &a, int width, int rows) {
+bool fused2_supported(int nd, int nl, int nn, bool identity) {
+    return nd == 3 && identity && nl <= 8 && nn == nl;
+}
+
+// PF_KERNEL_AUTO takes two iterations per pass for 3-D Potts with float32
+// state (measured faster than the one-iteration pass there); with 16-bit
+// state the two-pass kernels stay faster.
+bool fused2_preferred(int nd, int nl, int nn, bool identity, int storage) {
+    return storage == PF_FP32 && fused2_supported(nd, nl, nn, identity);
+}
+
+// One block per compute unit (its register and LDS use allow no second one):
+// about 256 blocks, i.e. few long z chunks; each chunk recomputes about three
+// planes of the first iteration.
+FusedGeom fused2_geometry(const StepArgs &a) { return tile_geometry(a, TW, TH, 256); }
+
+FusedGeom tile_geometry(const StepArgs &a, int width, int rows, long target) {
     FusedGeom g{};
     g.tiles_x = (a.nx + width - 1) / width;
     g.tiles_y = (a.ny + rows - 1) / rows;
     const long tiles = (long)g.tiles_x * g.tiles_y * a.B;
-    // aim for about two resident blocks per compute unit on 256 CUs, with
+    // by default about two resident blocks per compute unit on 256 CUs, with
     // chunks of at least 16 planes (each chunk recomputes one extra plane)
-    const long target = 512;
     long chunks = (target + tiles - 1) / tiles;
     const long max_chunks = (a.nz + 15) / 16;
     if (chunks > max_chunks) chunks = max_chunks;
@@ -295,6 +542,22 @@ hipError_t launch_fused(const StepArgs &a, bool ident, int nd, int storage, hipS
                                   <<<(unsigned)g.blocks, FTHREADS, 0, s>>>(a, g);
                               return hipGetLastError();
                           });
+}
+
+hipError_t launch_fused2(const StepArgs &a, int storage, hipStream_t s) {
+    if (!fused2_supported(3, a.nl, a.nn, true) || a.nz < 1) return hipErrorInvalidValue;
+    const FusedGeom g = fused2_geometry(a);
+    if (g.blocks <= 0 || g.blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    auto go = [&]<int NL, typename T>() {
+        k_fused2<NL, T><<<(unsigned)g.blocks, T2THREADS, 0, s>>>(a, g);
+        return hipGetLastError();
+    };
+    auto by = [&]<typename T>() {
+        return a.nl <= 4 ? go.template operator()<4, T>() : go.template operator()<8, T>();
+    };
+    if (storage == PF_BF16) return by.template operator()<bf16s>();
+    if (storage == PF_FP16) return by.template operator()<f16s>();
+    return by.template operator()<float>();
 }
 
 }  // namespace pf

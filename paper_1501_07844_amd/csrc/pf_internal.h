@@ -107,8 +107,14 @@ hipError_t launch_fused(const StepArgs &a, bool ident, int nd, int storage, hipS
 bool fused_supported(int nd, int nl, int nn, bool identity);
 bool fused_preferred(int nd, int nl, int nn, bool identity, int storage);
 FusedGeom fused_geometry(const StepArgs &a);
-// tiles of width x rows voxels, z chunks, problems (the z-marching kernels)
-FusedGeom tile_geometry(const StepArgs &a, int width, int rows);
+// two iterations per launch (3-D Potts, up to 8 labels), ping-pong state
+hipError_t launch_fused2(const StepArgs &a, int storage, hipStream_t s);
+bool fused2_supported(int nd, int nl, int nn, bool identity);
+bool fused2_preferred(int nd, int nl, int nn, bool identity, int storage);
+FusedGeom fused2_geometry(const StepArgs &a);
+// tiles of width x rows voxels, z chunks, problems (the z-marching kernels);
+// about `target` blocks, chunks of at least 16 planes
+FusedGeom tile_geometry(const StepArgs &a, int width, int rows, long target = 512);
 hipError_t launch_copy_state(const StepArgs &a, int nd, int storage, hipStream_t s);
 hipError_t launch_energy(const StepArgs &a, bool ident, int nd, int storage,
                          double *partials, double *results, hipStream_t s);

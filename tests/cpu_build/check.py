@@ -4,12 +4,13 @@ AddressSanitizer and UBSan, driven through the C ABI with host buffers.
 
 1. Forward: the fused and the two-pass iteration give the same state, energy
    and dual bit for bit (fp32, bf16, fp16; odd label and flow counts, ragged
-   tiles, several z chunks).
+   tiles, several z chunks), and so does the two-iterations-per-pass kernel
+   (odd iteration counts and gap checks mixing in one-iteration passes).
 2. Reverse: recorded forward + backward against autograd through the float64
    reference implementation, and the fused reverse step bit for bit against
    the two-kernel one.
 
-Usage: python check.py path/to/libcpu.so
+Usage: python check.py path/to/libcpu.so [forward] [fused2] [reverse]
 """
 import ctypes as C
 import os
@@ -39,7 +40,7 @@ def ptr(a):
     return C.c_void_p(a.ctypes.data)
 
 
-def solve(p, iters, kernel, storage, tape=None, every=0, want_ell=False):
+def solve(p, iters, kernel, storage, tape=None, every=0, want_ell=False, gap_every=0):
     B, Z, Y, X = p.shape
     nl, nn = p.n_leaf, p.n_node
     D = np.ascontiguousarray(p.D, np.float32)
@@ -49,6 +50,7 @@ def solve(p, iters, kernel, storage, tape=None, every=0, want_ell=False):
     prm = pf._Params()
     prm.iters, prm.c, prm.tau = iters, p.c, p.tau
     prm.storage, prm.kernel, prm.final_energy = pf.STORAGE[storage], pf.KERNEL[kernel], 1
+    prm.gap_every = gap_every
     need = lib.pf_workspace_bytes(C.byref(grid), nl, nn, C.byref(prm))
     wraw, wptr = aligned(need)
     keep.append(wraw)
@@ -94,6 +96,28 @@ def check_forward():
             b = solve(p, iters, "fused", storage)
             same = all(np.array_equal(x, y) for x, y in zip(a[:2], b[:2])) and a[3:] == b[3:]
             print(f"forward {name:24s} {storage}: fused == two-pass bitwise: {same}", flush=True)
+            bad += not same
+    return bad
+
+
+def fused2_cases():
+    return [
+        ("potts3d nl3 B2 chunks", synth.random_potts(1, (40, 10, 140), 3, 3, batch=2, s_mode="node_field"), 5, 0),
+        ("potts3d nl8 scalar", synth.random_potts(3, (34, 9, 130), 3, 8, s_mode="node_scalar"), 4, 0),
+        ("potts3d nl5 shared gap3", synth.random_potts(5, (35, 17, 66), 3, 5, s_mode="shared_field"), 7, 3),
+        ("potts3d nl4 thin", synth.random_potts(6, (2, 3, 70), 3, 4, s_mode="node_scalar"), 4, 0),
+    ]
+
+
+def check_fused2():
+    """Two iterations per pass against the one-iteration fused kernel."""
+    bad = 0
+    for name, p, iters, gap_every in fused2_cases():
+        for storage in ("fp32", "bf16", "fp16"):
+            a = solve(p, iters, "fused", storage, gap_every=gap_every)
+            b = solve(p, iters, "fused2", storage, gap_every=gap_every)
+            same = all(np.array_equal(x, y) for x, y in zip(a[:2], b[:2])) and a[3:] == b[3:]
+            print(f"forward {name:24s} {storage}: two-iteration == fused bitwise: {same}", flush=True)
             bad += not same
     return bad
 
@@ -184,6 +208,13 @@ def check_reverse():
 
 if __name__ == "__main__":
     torch.set_num_threads(min(8, torch.get_num_threads()))
-    n_bad = check_forward() + check_reverse()
+    only = sys.argv[2:]
+    n_bad = 0
+    if not only or "forward" in only:
+        n_bad += check_forward()
+    if not only or "fused2" in only:
+        n_bad += check_fused2()
+    if not only or "reverse" in only:
+        n_bad += check_reverse()
     print("ALL OK" if n_bad == 0 else f"{n_bad} FAILED")
     sys.exit(1 if n_bad else 0)

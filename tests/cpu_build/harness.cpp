@@ -125,6 +125,15 @@ hipError_t launch_fused(const StepArgs &a, bool ident, int nd, int st, hipStream
     };
     return disp(nd, st, ident, a.nl, a.nn, f);
 }
+hipError_t launch_fused2(const StepArgs &a, int st, hipStream_t) {
+    if (!fused2_supported(3, a.nl, a.nn, true) || a.nz < 1) return 1;
+    const FusedGeom g = fused2_geometry(a);
+    return dtype(st, [&]<typename T>() {
+        if (a.nl <= 4) run_grid(dim3((unsigned)g.blocks), T2THREADS, true, [&] { k_fused2<4, T>(a, g); });
+        else run_grid(dim3((unsigned)g.blocks), T2THREADS, true, [&] { k_fused2<8, T>(a, g); });
+        return 0;
+    });
+}
 hipError_t launch_energy(const StepArgs &a, bool ident, int nd, int st, double *partials, double *results,
                          hipStream_t) {
     // fewer blocks than the library (64, not kPartials) keep the threaded run

@@ -78,8 +78,8 @@ def gpu_solve(p, iters=None, **kw):
             return pf.solve_hmf(D, S, p.graph, **args)
         return pf.solve_dagmf(D, S, p.graph, **args)
     except pf.PseudoflowError as e:
-        if e.code == pf.PF_EUNSUPPORTED and kw.get("kernel") == "fused":
-            pytest.skip("no fused kernel for this problem in this build")
+        if e.code == pf.PF_EUNSUPPORTED and kw.get("kernel") in ("fused", "fused2"):
+            pytest.skip(f"no {kw['kernel']} kernel for this problem in this build")
         raise
 
 

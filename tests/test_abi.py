@@ -60,6 +60,26 @@ def _params(**kw):
     return p
 
 
+def test_auto_kernel_choice():
+    """The kernel AUTO resolves to: two iterations per pass for 3-D Potts
+    with float32 state up to 8 labels, the one-iteration fused pass beyond,
+    the two-pass kernels for 16-bit state, 2-D problems and label graphs."""
+    k = pf.KERNEL
+    assert pf.auto_kernel((1, 256, 256, 256), 8, 8, 3) == "fused2"
+    assert pf.auto_kernel((2, 5, 7, 9), 3, 3, 3) == "fused2"
+    assert pf.auto_kernel((1, 16, 16, 16), 12, 12, 3) == "fused"
+    assert pf.auto_kernel((1, 16, 16, 16), 8, 8, 3, "bf16") == "two_pass"
+    assert pf.auto_kernel((1, 1, 64, 64), 8, 8, 2) == "two_pass"
+    assert pf.auto_kernel((1, 16, 16, 16), 8, 11, 3, identity=False) == "two_pass"
+    lib = pf.library()
+    assert lib.pf_auto_kernel(C.byref(_grid()), 4, 5, 1, 0) == -1          # Potts needs n_node == n_leaf
+    assert lib.pf_auto_kernel(C.byref(_grid()), 4, 4, 1, 9) == -1          # storage
+    assert lib.pf_auto_kernel(None, 4, 4, 1, 0) == -1
+    assert lib.pf_auto_kernel(C.byref(_grid()), 4, 4, 1, 0) == k["fused2"]
+    with pytest.raises(ValueError):
+        pf.auto_kernel((1, 4, 4, 4), 17, 17, 3)
+
+
 def test_workspace_bytes_accounting():
     lib = pf.library()
     g = _grid(2, 3, 8, 9, 10)
@@ -141,7 +161,9 @@ DEV = 1 << 20          # fake aligned pointers
     ("null_ws", pf.PF_EINVAL), ("misaligned_ws", pf.PF_EINVAL), ("small_ws", pf.PF_ENOMEM),
     ("too_many_labels", pf.PF_EUNSUPPORTED), ("bad_storage", pf.PF_EINVAL),
     ("neg_S", pf.PF_EINVAL), ("nan_S", pf.PF_ENONFINITE), ("bad_smode", pf.PF_EINVAL),
-    ("null_params", pf.PF_EINVAL),
+    ("null_params", pf.PF_EINVAL), ("bad_kernel", pf.PF_EINVAL),
+    ("fused2_2d", pf.PF_EUNSUPPORTED), ("fused2_9_labels", pf.PF_EUNSUPPORTED),
+    ("fused2_recorded", pf.PF_EUNSUPPORTED),
 ])
 def test_potts_argument_errors(case, code):
     g, n, D, S, mode, p = _grid(), 3, DEV, SADDR, 0, _params()
@@ -183,6 +205,19 @@ def test_potts_argument_errors(case, code):
         mode = 9
     elif case == "null_params":
         p = None
+    elif case == "bad_kernel":
+        p.kernel = 4
+    elif case == "fused2_2d":
+        g = _grid(1, 2, 1, 9, 10)
+        p.kernel = pf.KERNEL["fused2"]
+    elif case == "fused2_9_labels":
+        n = 9
+        keep = (C.c_float * 9)(*([0.5] * 9))
+        S = C.addressof(keep)
+        p.kernel = pf.KERNEL["fused2"]
+    elif case == "fused2_recorded":
+        p.kernel = pf.KERNEL["fused2"]
+        p.ckpt_every, p.tape, p.tape_bytes = 1, 512 * 1024, 1 << 30
     assert _call_potts(g, n, D, S, mode, p) == code
     assert pf.library().pf_last_error().decode() != ""
 

@@ -17,13 +17,15 @@ from parity_util import (check_parity, compare_labels, gpu_solve, oracle_energy_
 pytestmark = pytest.mark.gpu
 torch.set_num_threads(max(1, min(16, torch.get_num_threads())))
 
-KERNELS = ["two_pass", "fused"]
+KERNELS = ["two_pass", "fused", "fused2"]
 
 
 def _kernels_for(p):
     ks = ["two_pass"]
     if p.kind in ("potts", "hmf", "dagmf"):
         ks.append("fused")
+    if p.kind == "potts" and p.ndim == 3 and p.n_leaf <= 8:
+        ks.append("fused2")
     return ks
 
 
@@ -50,7 +52,7 @@ WORKLOADS = {
 def test_workload_parity(name, kernel):
     p = WORKLOADS[name]()
     if kernel not in _kernels_for(p):
-        pytest.skip("no fused kernel for this model")
+        pytest.skip(f"no {kernel} kernel for this model")
     print(f"[parity] {name} kernel={kernel} shape={p.shape} iters={p.iters}", flush=True)
     _run_and_check(p, kernel)
 
@@ -211,6 +213,56 @@ def test_fused_equals_two_pass_bitwise(name, storage):
     b = gpu_solve(p, 40, kernel="fused", storage=storage, return_q=True)
     assert torch.equal(a.u, b.u) and torch.equal(a.q, b.q) and torch.equal(a.labels, b.labels)
     assert a.energy == b.energy and a.dual == b.dual
+
+
+FUSED2_CASES = {
+    "potts3d_voronoi_36x40x44": lambda: WORKLOADS["potts3d_voronoi_36x40x44"](),
+    "potts3d_nl3_B2_nodefield": lambda: synth.random_potts(21, (37, 19, 131), 3, 3, batch=2,
+                                                           s_mode="node_field"),
+    "potts3d_nl5_shared": lambda: synth.random_potts(22, (33, 17, 70), 3, 5, s_mode="shared_field"),
+    "potts3d_nl8_thin": lambda: synth.random_potts(23, (2, 9, 65), 3, 8, s_mode="node_scalar"),
+}
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("name", list(FUSED2_CASES))
+def test_fused2_equals_fused_bitwise(name, storage):
+    """Two iterations per pass evaluate each point's expressions of the
+    one-iteration kernels, with the intermediate state rounded where those
+    store it, so the states agree bit for bit; with an odd count and gap
+    checks every 5 iterations, one-iteration passes mix in."""
+    p = FUSED2_CASES[name]()
+    for iters, gap_every in ((40, 0), (23, 5)):
+        print(f"[fused2] {name} {storage} iters={iters} gap_every={gap_every}", flush=True)
+        a = gpu_solve(p, iters, kernel="fused", storage=storage, return_q=True, gap_every=gap_every)
+        b = gpu_solve(p, iters, kernel="fused2", storage=storage, return_q=True, gap_every=gap_every)
+        assert torch.equal(a.u, b.u) and torch.equal(a.q, b.q) and torch.equal(a.labels, b.labels)
+        assert a.energy == b.energy and a.dual == b.dual
+        assert a.iters_done == b.iters_done == iters
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+def test_fused2_full_size_equals_fused(storage):
+    """At the full 256^3 Potts workload in the benchmark's launch
+    configuration: six iterations as three two-iteration passes equal six
+    one-iteration passes bit for bit."""
+    p = synth.potts3d_voronoi(n=256, iters=6)
+    D, S = torch.from_numpy(p.D).cuda(), torch.from_numpy(p.S).cuda()
+    kw = dict(c=p.c, tau=p.tau, iters=6, ndim=3, s_mode="shared_field", storage=storage,
+              return_q=True, final_energy=True)
+    a = pf.solve_potts(D, S, kernel="fused", **kw)
+    b = pf.solve_potts(D, S, kernel="fused2", **kw)
+    assert torch.equal(a.u, b.u) and torch.equal(a.q, b.q)
+    assert a.energy == b.energy and a.dual == b.dual
+
+
+def test_fused2_rejects_unsupported():
+    for p, why in ((synth.random_potts(1, (1, 9, 11), 2, 4), "2-D"),
+                   (synth.random_potts(2, (3, 5, 7), 3, 12), "12 labels"),
+                   (synth.hmf_ellipsoids(shape=(4, 6, 8), iters=2), "label graph")):
+        with pytest.raises(pf.PseudoflowError) as ei:
+            gpu_solve(p, 2, kernel="fused2")
+        assert ei.value.code == pf.PF_EUNSUPPORTED, why
 
 
 def _patch_bounds(x, n, w=5):
