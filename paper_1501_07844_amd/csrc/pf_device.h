@@ -59,12 +59,18 @@ __device__ __forceinline__ float wgt(const StepArgs &a, int A, int L) {
 // Start of field f of problem b in a [B][F][V] array: uniform across the
 // block, so that loads become "uniform base + 32-bit lane offset" (the
 // global saddr form, one offset VGPR shared by every field of a voxel).
-template <typename T>
+// N32 forms the field index b*F + f in 32 bits (B*F is far below 2^31) and
+// widens it once for the product with V; the result is the same, the scalar
+// code differs (N32 measured faster in the two-iteration kernel and slower in
+// the one-iteration one, so each kernel picks its form).
+template <typename T, bool N32 = false>
 __device__ __forceinline__ const T *field(const void *base, int b, int nf, int f, size_t V) {
+    if constexpr (N32) return static_cast<const T *>(base) + (size_t)(uint32_t)(b * nf + f) * V;
     return static_cast<const T *>(base) + ((size_t)b * nf + f) * V;
 }
-template <typename T>
+template <typename T, bool N32 = false>
 __device__ __forceinline__ T *field_w(void *base, int b, int nf, int f, size_t V) {
+    if constexpr (N32) return static_cast<T *>(base) + (size_t)(uint32_t)(b * nf + f) * V;
     return static_cast<T *>(base) + ((size_t)b * nf + f) * V;
 }
 
@@ -117,62 +123,62 @@ __device__ __forceinline__ uint32_t pack2(float lo, float hi, const f16s *) {
 // valid field (clamped; the caller masks it), and the clamp is taken on the
 // word index for packed state, so that L = 2P and 2P + 1 load the same word
 // and the compiler merges the two loads.
-template <typename T>
+template <typename T, bool N32 = false>
 __device__ __forceinline__ float ld_ell(const void *base, int b, int nl, int L, size_t V, unsigned uv) {
     if constexpr (kPacked<T>) {
         const int np = (nl + 1) / 2, P = L >> 1;
-        const uint32_t *p = field<uint32_t>(base, b, np, P < np ? P : np - 1, V);
+        const uint32_t *p = field<uint32_t, N32>(base, b, np, P < np ? P : np - 1, V);
         const uint32_t w = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(p) + uv * 4u);
         return half_of(w, L & 1, static_cast<const T *>(nullptr));
     } else {
-        return ldf(field<float>(base, b, nl, L < nl ? L : nl - 1, V), uv);
+        return ldf(field<float, N32>(base, b, nl, L < nl ? L : nl - 1, V), uv);
     }
 }
 
 // Component k of flow A of problem b at voxel index uv (A clamped as L above).
-template <typename T, int ND>
+template <typename T, int ND, bool N32 = false>
 __device__ __forceinline__ float ld_q(const void *base, int b, int nn, int A, int k, size_t V,
                                       unsigned uv) {
     if constexpr (kPacked<T>) {
         const int np = (nn + 1) / 2, P = A >> 1;
-        const uint32_t *p = field<uint32_t>(base, b, np * ND, (P < np ? P : np - 1) * ND + k, V);
+        const uint32_t *p = field<uint32_t, N32>(base, b, np * ND, (P < np ? P : np - 1) * ND + k, V);
         const uint32_t w = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(p) + uv * 4u);
         return half_of(w, A & 1, static_cast<const T *>(nullptr));
     } else {
-        return ldf(field<float>(base, b, nn * ND, (A < nn ? A : nn - 1) * ND + k, V), uv);
+        return ldf(field<float, N32>(base, b, nn * ND, (A < nn ? A : nn - 1) * ND + k, V), uv);
     }
 }
 
 // Labels L and L + 1 (L even) at voxel uv; nothing past nl is stored (a
 // packed word's spare half gets 0).
-template <typename T>
+template <typename T, bool N32 = false>
 __device__ __forceinline__ void st_ell2(void *base, int b, int nl, int L, size_t V, unsigned uv,
                                         float lo, float hi) {
     if constexpr (kPacked<T>) {
         if (L < nl) {
-            uint32_t *p = field_w<uint32_t>(base, b, (nl + 1) / 2, L >> 1, V);
+            uint32_t *p = field_w<uint32_t, N32>(base, b, (nl + 1) / 2, L >> 1, V);
             *reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(p) + uv * 4u) =
                 pack2(lo, L + 1 < nl ? hi : 0.f, static_cast<const T *>(nullptr));
         }
     } else {
-        if (L < nl) sto(field_w<float>(base, b, nl, L, V), uv, lo);
-        if (L + 1 < nl) sto(field_w<float>(base, b, nl, L + 1, V), uv, hi);
+        if (L < nl) sto(field_w<float, N32>(base, b, nl, L, V), uv, lo);
+        if (L + 1 < nl) sto(field_w<float, N32>(base, b, nl, L + 1, V), uv, hi);
     }
 }
 
 // Component k of flows A and A + 1 (A even) at voxel uv.
-template <typename T, int ND>
+template <typename T, int ND, bool N32 = false>
 __device__ __forceinline__ void st_q2(void *base, int b, int nn, int A, int k, size_t V,
                                       unsigned uv, float lo, float hi) {
     if constexpr (kPacked<T>) {
         if (A < nn) {
-            uint32_t *p = field_w<uint32_t>(base, b, (nn + 1) / 2 * ND, (A >> 1) * ND + k, V);
+            uint32_t *p = field_w<uint32_t, N32>(base, b, (nn + 1) / 2 * ND, (A >> 1) * ND + k, V);
             *reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(p) + uv * 4u) =
                 pack2(lo, A + 1 < nn ? hi : 0.f, static_cast<const T *>(nullptr));
         }
     } else {
-        if (A < nn) sto(field_w<float>(base, b, nn * ND, A * ND + k, V), uv, lo);
-        if (A + 1 < nn) sto(field_w<float>(base, b, nn * ND, (A + 1) * ND + k, V), uv, hi);
+        if (A < nn) sto(field_w<float, N32>(base, b, nn * ND, A * ND + k, V), uv, lo);
+        if (A + 1 < nn) sto(field_w<float, N32>(base, b, nn * ND, (A + 1) * ND + k, V), uv, hi);
     }
 }
 

@@ -45,7 +45,7 @@ constexpr int FTHREADS = FTX * (FTY + 2);   // owned rows + the halo row + the h
 // load returns), the new labels u = exp(er) (what the two-pass flow kernel
 // reads back), the old flows at the voxel in qpt, and stores the new
 // log-labels when `store`.  All loads are issued first, unconditionally.
-template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T>
+template <int ND, int NLMAX, int NNMAX, bool IDENT, typename T, bool N32 = false>
 __device__ __forceinline__ void label_point(const StepArgs &a, int b, int x, int y, int z,
                                             const float (&qzb)[NNMAX], bool store,
                                             float (&u)[NLMAX], float (&qpt)[NNMAX][ND],
@@ -62,16 +62,16 @@ __device__ __forceinline__ void label_point(const StepArgs &a, int b, int x, int
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L) {
         const int Lc = L < a.nl ? L : a.nl - 1;
-        d[L] = ldf(field<float>(a.D, b, a.nl, Lc, V), uv);
-        e[L] = ld_ell<T>(a.ell_in, b, a.nl, L, V, uv);
+        d[L] = ldf(field<float, N32>(a.D, b, a.nl, Lc, V), uv);
+        e[L] = ld_ell<T, N32>(a.ell_in, b, a.nl, L, V, uv);
     }
 #pragma unroll
     for (int A = 0; A < NNMAX; ++A) {
-        qpt[A][0] = ld_q<T, ND>(a.q_in, b, a.nn, A, 0, V, uv);
-        qpt[A][1] = ld_q<T, ND>(a.q_in, b, a.nn, A, 1, V, uv);
-        if constexpr (ND == 3) qpt[A][2] = ld_q<T, ND>(a.q_in, b, a.nn, A, 2, V, uv);
-        qm[A][0] = ld_q<T, ND>(a.q_in, b, a.nn, A, 0, V, uv - (unsigned)m[0]);
-        qm[A][1] = ld_q<T, ND>(a.q_in, b, a.nn, A, 1, V, uv - (unsigned)m[1]);
+        qpt[A][0] = ld_q<T, ND, N32>(a.q_in, b, a.nn, A, 0, V, uv);
+        qpt[A][1] = ld_q<T, ND, N32>(a.q_in, b, a.nn, A, 1, V, uv);
+        if constexpr (ND == 3) qpt[A][2] = ld_q<T, ND, N32>(a.q_in, b, a.nn, A, 2, V, uv);
+        qm[A][0] = ld_q<T, ND, N32>(a.q_in, b, a.nn, A, 0, V, uv - (unsigned)m[0]);
+        qm[A][1] = ld_q<T, ND, N32>(a.q_in, b, a.nn, A, 1, V, uv - (unsigned)m[1]);
         qm[A][2] = ND == 3 ? qzb[A] : 0.f;
     }
 #pragma unroll
@@ -82,7 +82,7 @@ __device__ __forceinline__ void label_point(const StepArgs &a, int b, int x, int
     entropic_step<NLMAX>(a, d, e);
     if (store) {
 #pragma unroll
-        for (int L = 0; L < NLMAX; L += 2) st_ell2<T>(a.ell_out, b, a.nl, L, V, uv, e[L], e[L + 1]);
+        for (int L = 0; L < NLMAX; L += 2) st_ell2<T, N32>(a.ell_out, b, a.nl, L, V, uv, e[L], e[L + 1]);
     }
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L) {
@@ -304,8 +304,8 @@ __global__ __launch_bounds__(T2THREADS) void k_fused2(StepArgs a, FusedGeom g) {
         float qzb[NN], u[NL], er[NL];
 #pragma unroll
         for (int A = 0; A < NN; ++A)
-            qzb[A] = zs >= 2 ? ld_q<T, 3>(a.q_in, b, a.nn, A, 2, V, vox(zs - 2)) : 0.f;
-        label_point<3, NL, NN, true, T>(a, b, x, y, zs - 1, qzb, false, u, q0c, er);
+            qzb[A] = zs >= 2 ? ld_q<T, 3, true>(a.q_in, b, a.nn, A, 2, V, vox(zs - 2)) : 0.f;
+        label_point<3, NL, NN, true, T, true>(a, b, x, y, zs - 1, qzb, false, u, q0c, er);
 #pragma unroll
         for (int L = 0; L < NL; ++L) lu1[L][r][c] = u[L];
     }
@@ -337,11 +337,11 @@ __global__ __launch_bounds__(T2THREADS) void k_fused2(StepArgs a, FusedGeom g) {
         if (doA) {
 #pragma unroll
             for (int L = 0; L < NL; ++L)
-                dn[L] = ldf(field<float>(a.D, b, a.nl, L < a.nl ? L : a.nl - 1, V), vox(pA));
+                dn[L] = ldf(field<float, true>(a.D, b, a.nl, L < a.nl ? L : a.nl - 1, V), vox(pA));
             float qzb[NN];
 #pragma unroll
             for (int A = 0; A < NN; ++A) qzb[A] = q0c[A][2];
-            label_point<3, NL, NN, true, T>(a, b, x, y, pA, qzb, false, u1n, q0n, e1n);
+            label_point<3, NL, NN, true, T, true>(a, b, x, y, pA, qzb, false, u1n, q0n, e1n);
         }
 
         // B: first flow step, plane z + 1
@@ -402,7 +402,7 @@ __global__ __launch_bounds__(T2THREADS) void k_fused2(StepArgs a, FusedGeom g) {
             entropic_step<NL>(a, d, e);
             if (own && pB < ze) {
 #pragma unroll
-                for (int L = 0; L < NL; L += 2) st_ell2<T>(a.ell_out, b, a.nl, L, V, uv, e[L], e[L + 1]);
+                for (int L = 0; L < NL; L += 2) st_ell2<T, true>(a.ell_out, b, a.nl, L, V, uv, e[L], e[L + 1]);
             }
 #pragma unroll
             for (int L = 0; L < NL; ++L) u2n[L] = __expf(roundtrip(e[L], (const T *)Tn));
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(T2THREADS) void k_fused2(StepArgs a, FusedGeom g) {
                     }
 #pragma unroll
                     for (int k = 0; k < 3; ++k)
-                        st_q2<T, 3>(a.q_out, b, a.nn, A, k, V, v, p[0][k], p[1][k]);
+                        st_q2<T, 3, true>(a.q_out, b, a.nn, A, k, V, v, p[0][k], p[1][k]);
                 }
             }
         }
