@@ -293,7 +293,10 @@ def _solve(entry, D, S, n_leaf, n_node, *, graph=None, n_labels=None, c, tau, it
 def solve_potts(D, S, *, c: float, tau: float, iters: int, **kw) -> SolveResult:
     """Pseudo-flow Potts model.  D: device float32 [B][n][Z][Y][X].
     S: scalar or host sequence of n per-label constants, or a device field
-    [B][Z][Y][X] (shared) or [B][n][Z][Y][X] (per label)."""
+    [B][Z][Y][X] (shared) or [B][n][Z][Y][X] (per label).  ``kernel``:
+    "auto" (see ``auto_kernel``), "two_pass", "fused" (one pass per
+    iteration) or "fused2" (one pass per two iterations; 3-D, n <= 8); all
+    give the same result bit for bit."""
     n = int(D.shape[1])
     return _solve(library().solve_potts, D, S, n, n, n_labels=n, c=c, tau=tau, iters=iters, **kw)
 
