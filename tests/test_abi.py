@@ -163,7 +163,7 @@ DEV = 1 << 20          # fake aligned pointers
     ("neg_S", pf.PF_EINVAL), ("nan_S", pf.PF_ENONFINITE), ("bad_smode", pf.PF_EINVAL),
     ("null_params", pf.PF_EINVAL), ("bad_kernel", pf.PF_EINVAL),
     ("fused2_2d", pf.PF_EUNSUPPORTED), ("fused2_9_labels", pf.PF_EUNSUPPORTED),
-    ("fused2_recorded", pf.PF_EUNSUPPORTED),
+    ("fused2_recorded", pf.PF_EUNSUPPORTED), ("too_many_voxels", pf.PF_EUNSUPPORTED),
 ])
 def test_potts_argument_errors(case, code):
     g, n, D, S, mode, p = _grid(), 3, DEV, SADDR, 0, _params()
@@ -215,6 +215,8 @@ def test_potts_argument_errors(case, code):
         keep = (C.c_float * 9)(*([0.5] * 9))
         S = C.addressof(keep)
         p.kernel = pf.KERNEL["fused2"]
+    elif case == "too_many_voxels":
+        g = _grid(1, 3, 1023, 1024, 1024)      # 1022 planes of 1024^2 is the largest admitted
     elif case == "fused2_recorded":
         p.kernel = pf.KERNEL["fused2"]
         p.ckpt_every, p.tape, p.tape_bytes = 1, 512 * 1024, 1 << 30

@@ -265,6 +265,45 @@ def test_fused2_rejects_unsupported():
         assert ei.value.code == pf.PF_EUNSUPPORTED, why
 
 
+def test_largest_admitted_grid_two_iterations():
+    """The largest grid the library admits per problem, 1022 x 1024 x 1024
+    voxels (the voxel byte offsets reach 4.29e9, just below 2^32), 3-D Potts
+    with 2 labels and float32 state under AUTO (two iterations per pass):
+    after two iterations from the initial state, u and q at sampled voxels
+    (the last voxel and the corners included) match the float64 reference
+    run on 9^3 patches of the same inputs (exact there: two iterations reach
+    three voxels)."""
+    Z, Y, X = 1022, 1024, 1024
+    free, _ = torch.cuda.mem_get_info()
+    if free < 150e9:
+        pytest.skip(f"needs about 120 GB of device memory ({free / 1e9:.0f} GB free)")
+    assert pf.auto_kernel((1, Z, Y, X), 2, 2, 3) == "fused2"
+    g = torch.Generator(device="cuda").manual_seed(5)
+    D = torch.rand((1, 2, Z, Y, X), generator=g, device="cuda", dtype=torch.float32)
+    S = np.array([0.3, 0.25], np.float32)
+    c, tau = 1.0, 0.125
+    print(f"[max grid] {Z}x{Y}x{X}, 2 labels", flush=True)
+    r = pf.solve_potts(D, S, c=c, tau=tau, iters=2, ndim=3, return_q=True, final_energy=False)
+    rng = np.random.default_rng(97)
+    pts = [(int(rng.integers(0, Z)), int(rng.integers(0, Y)), int(rng.integers(0, X))) for _ in range(12)]
+    pts += [(0, 0, 0), (Z - 1, Y - 1, X - 1), (Z - 1, 0, X - 1), (0, Y - 1, 0), (Z // 2, Y - 1, X - 1)]
+    worst_u = worst_q = 0.0
+    for (z, y, x) in pts:
+        (z0, z1), (y0, y1), (x0, x1) = (_patch_bounds(z, Z, 9), _patch_bounds(y, Y, 9),
+                                        _patch_bounds(x, X, 9))
+        Dp = D[:, :, z0:z1, y0:y1, x0:x1].double().cpu()
+        ref = O.solve_potts(Dp, S.astype(np.float64), "node_scalar", c, tau, 2, 3, history=False)
+        cz, cy, cx = z - z0, y - y0, x - x0
+        u_gpu = r.u[0, :, z, y, x].double().cpu()
+        q_gpu = r.q[0, :, :, z, y, x].double().cpu()
+        worst_u = max(worst_u, float((ref["u"][0, :, cz, cy, cx] - u_gpu).abs().max()))
+        worst_q = max(worst_q, float((ref["q"][0, :, :, cz, cy, cx] - q_gpu).abs().max()))
+    print(f"[max grid] max|du| {worst_u:.2e}, max|dq| {worst_q:.2e}", flush=True)
+    del D, r
+    torch.cuda.empty_cache()
+    assert worst_u <= 1e-5 and worst_q <= 1e-5
+
+
 def _patch_bounds(x, n, w=5):
     lo = min(max(x - w // 2, 0), max(n - w, 0))
     return lo, min(lo + w, n)
