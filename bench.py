@@ -104,14 +104,17 @@ def kernel_leg(p, storage: str, iters: int, dev, kernel: str = "auto") -> dict:
     every launch bracketed by HIP events on the solver's stream; the mean
     per iteration (a k_fused2 launch covers two).  alg_GBs: algorithmic
     bytes of one iteration over the time per iteration; launch_alg_GBs: the
-    bytes one launch must move over its duration (the roofline figure)."""
+    bytes one launch must move over its duration (the roofline figure).
+    energy_full / rel_gap_full: final energy and relative gap of the warm-up
+    solve, run at the workload's own iteration budget (the figures the
+    16-bit storage types are compared on)."""
     import paper_1501_07844_amd as pf
     D, S = _inputs(p, dev)
     solve = _solver(pf, p)
-    kw = dict(c=p.c, tau=p.tau, iters=iters, ndim=p.ndim, s_mode=p.s_mode, storage=storage,
+    kw = dict(c=p.c, tau=p.tau, ndim=p.ndim, s_mode=p.s_mode, storage=storage,
               kernel=kernel, final_energy=True, return_u=False, return_labels=False)
-    r = solve(D, S, **kw)
-    r = solve(D, S, workspace=r.workspace, timing_stride=1, **kw)
+    full = solve(D, S, iters=p.iters, **kw)          # warm-up, and the energy at the full budget
+    r = solve(D, S, iters=iters, workspace=full.workspace, timing_stride=1, **kw)
     ms = r.kernel_ms / max(r.kernel_timed, 1)
     choice = _kernel_choice(pf, p, storage, kernel)
     per_launch = 2 if choice == "fused2" else 1
@@ -127,8 +130,10 @@ def kernel_leg(p, storage: str, iters: int, dev, kernel: str = "auto") -> dict:
            "voxel_label_its_per_s": V * p.n_node / (ms * 1e-3),
            "alg_bytes_per_voxel": ba, "alg_GBs": round(achieved, 1),
            "launch_alg_GBs": round(launch, 1),
-           "hbm_frac": round(launch / HBM_PEAK_GBS, 4), "energy": r.energy}
-    del D, S, r
+           "hbm_frac": round(launch / HBM_PEAK_GBS, 4), "energy": r.energy,
+           "iterations_full": p.iters, "energy_full": full.energy,
+           "rel_gap_full": full.gap / abs(full.energy)}
+    del D, S, r, full
     return out
 
 
@@ -415,6 +420,8 @@ def main() -> int:
                 legs[i + j]["speedup_vs_fp32"] = round(legs[i]["ms_per_iter"] / legs[i + j]["ms_per_iter"], 3)
                 legs[i + j]["rel_energy_vs_fp32"] = (abs(legs[i + j]["energy"] - legs[i]["energy"])
                                                      / abs(legs[i]["energy"]))
+                legs[i + j]["rel_energy_full_vs_fp32"] = (
+                    abs(legs[i + j]["energy_full"] - legs[i]["energy_full"]) / abs(legs[i]["energy_full"]))
         out["workloads"] = legs
         out["potts2d"] = potts2d_leg(dev)
         out["ishikawa2d"] = ishikawa2d_leg(dev)
