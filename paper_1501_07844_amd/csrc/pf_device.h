@@ -24,12 +24,15 @@ __device__ __forceinline__ float ld(const bf16s *p, size_t i) {
 }
 __device__ __forceinline__ float ld(const f16s *p, size_t i) { return (float)p[i]; }
 
-// float -> bf16 bits, round to nearest even; NaN stays a quiet NaN
+// float -> bf16 bits, round to nearest even (gfx950 converts in hardware:
+// v_cvt_pk_bf16_f32, two values per instruction)
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t bf16_bits(float v) {
-    uint32_t u = __float_as_uint(v);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
+    const __bf16 h = (__bf16)v;
+    uint16_t r;
+    __builtin_memcpy(&r, &h, 2);
+    return r;
 }
 __device__ __forceinline__ uint32_t f16_bits(float v) {
     const f16s h = (f16s)v;
@@ -113,7 +116,11 @@ __device__ __forceinline__ float half_of(uint32_t w, int h, const f16s *) {
     return (float)x;
 }
 __device__ __forceinline__ uint32_t pack2(float lo, float hi, const bf16s *) {
-    return bf16_bits(lo) | (bf16_bits(hi) << 16);
+    const f32x2_t v = {lo, hi};
+    const bf16x2_t h = __builtin_convertvector(v, bf16x2_t);
+    uint32_t w;
+    __builtin_memcpy(&w, &h, 4);
+    return w;
 }
 __device__ __forceinline__ uint32_t pack2(float lo, float hi, const f16s *) {
     return f16_bits(lo) | (f16_bits(hi) << 16);

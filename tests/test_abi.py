@@ -62,13 +62,16 @@ def _params(**kw):
 
 def test_auto_kernel_choice():
     """The kernel AUTO resolves to: two iterations per pass for 3-D Potts
-    with float32 state up to 8 labels, the one-iteration fused pass beyond,
-    the two-pass kernels for 16-bit state, 2-D problems and label graphs."""
+    up to 8 labels in every storage type, the one-iteration fused pass
+    beyond with float32 state, the two-pass kernels for 16-bit state beyond
+    8 labels, 2-D problems and label graphs."""
     k = pf.KERNEL
     assert pf.auto_kernel((1, 256, 256, 256), 8, 8, 3) == "fused2"
     assert pf.auto_kernel((2, 5, 7, 9), 3, 3, 3) == "fused2"
     assert pf.auto_kernel((1, 16, 16, 16), 12, 12, 3) == "fused"
-    assert pf.auto_kernel((1, 16, 16, 16), 8, 8, 3, "bf16") == "two_pass"
+    assert pf.auto_kernel((1, 16, 16, 16), 8, 8, 3, "bf16") == "fused2"
+    assert pf.auto_kernel((1, 16, 16, 16), 8, 8, 3, "fp16") == "fused2"
+    assert pf.auto_kernel((1, 16, 16, 16), 12, 12, 3, "bf16") == "two_pass"
     assert pf.auto_kernel((1, 1, 64, 64), 8, 8, 2) == "two_pass"
     assert pf.auto_kernel((1, 16, 16, 16), 8, 11, 3, identity=False) == "two_pass"
     lib = pf.library()

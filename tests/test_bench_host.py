@@ -39,7 +39,7 @@ def test_algorithmic_bytes_per_voxel(make, storage, expected):
 def test_kernel_choice_per_workload():
     p = synth.potts3d_voronoi(shape=(8, 8, 8))
     assert bench._kernel_choice(pf, p, "fp32", "auto") == "fused2"
-    assert bench._kernel_choice(pf, p, "bf16", "auto") == "two_pass"
+    assert bench._kernel_choice(pf, p, "bf16", "auto") == "fused2"
     assert bench._kernel_choice(pf, p, "fp32", "fused") == "fused"
     assert bench._kernel_choice(pf, synth.hmf_ellipsoids(shape=(4, 5, 6)), "fp32", "auto") == "two_pass"
     assert bench._kernel_choice(pf, synth.dagmf_blobs(shape=(4, 5, 6)), "fp32", "auto") == "two_pass"
