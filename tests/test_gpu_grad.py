@@ -227,3 +227,74 @@ def test_full_size_diff_batch_sampled():
     assert eD <= 1e-3 and eS <= 1e-3
     assert np.isfinite(gD).all() and np.isfinite(gS).all()
     assert all(np.abs(gD[i]).max() > 0 for i in range(B))
+
+
+def test_full_size_diff_batch_central_differences():
+    """The differentiation workload as specified: 16 Potts problems of
+    256 x 256, 5 labels, 100 unrolled iterations, checkpoint every 10, loss =
+    mean cross-entropy against the ground-truth labels.  The GPU gradient at
+    8 random entries of D and 8 of S (seed 55) against float64 central
+    differences (h = 1e-6) of the same loss through the oracle.  Most
+    uniformly drawn entries lie inside a region, where the gradient is 0 or
+    nearly so, so 8 more of each are drawn among voxels on a ground-truth
+    class boundary (a 4-neighbour of another class; for D the voxel's own
+    class), where it is larger, though often still below what differences
+    with h = 1e-6 resolve on a loss of order 0.1 (about 1e-11).  A
+    perturbed entry changes only its own problem, so each difference solves
+    that one problem (all perturbed copies in one batched oracle call)."""
+    import os
+    torch.set_num_threads(min(16, os.cpu_count() or 1))
+    p = synth.diff_batch()
+    B, nl, _, Y, X = p.D.shape
+    S0 = np.asarray(p.S, np.float32)
+    D = torch.from_numpy(p.D).cuda().requires_grad_(True)
+    S = torch.from_numpy(S0).cuda().requires_grad_(True)
+    gt = torch.from_numpy(p.gt.astype(np.int64)).cuda()
+    ell = pf.potts_layer(D, S, c=p.c, tau=p.tau, iters=p.iters, ckpt_every=p.extra["checkpoint_every"])
+    (-torch.gather(ell, 1, gt.unsqueeze(1)).mean()).backward()
+    torch.cuda.synchronize()
+    gD, gS = D.grad.cpu().numpy(), S.grad.cpu().numpy()
+    rng = np.random.default_rng(55)
+    picks = [("D", np.unravel_index(i, p.D.shape)) for i in rng.choice(p.D.size, 8, replace=False)]
+    picks += [("S", np.unravel_index(i, S0.shape)) for i in rng.choice(S0.size, 8, replace=False)]
+    g2 = p.gt[:, 0]                                                   # [B][Y][X]
+    edge = np.zeros(g2.shape, bool)
+    edge[:, 1:, :] |= g2[:, 1:, :] != g2[:, :-1, :]
+    edge[:, :-1, :] |= g2[:, 1:, :] != g2[:, :-1, :]
+    edge[:, :, 1:] |= g2[:, :, 1:] != g2[:, :, :-1]
+    edge[:, :, :-1] |= g2[:, :, 1:] != g2[:, :, :-1]
+    eb, ey, ex = np.nonzero(edge)
+    for which in ("D", "S"):
+        for i in rng.choice(eb.size, 8, replace=False):
+            if which == "D":       # the data term of the voxel's own class
+                picks.append(("D", (eb[i], int(g2[eb[i], ey[i], ex[i]]), 0, ey[i], ex[i])))
+            else:
+                picks.append(("S", (eb[i], 0, ey[i], ex[i])))
+    Ds, Ss, gts = [], [], []
+    for which, idx in picks:
+        b = int(idx[0])
+        for sign in (1.0, -1.0):
+            Db = p.D[b:b + 1].astype(np.float64)
+            Sb = S0[b:b + 1].astype(np.float64)
+            (Db if which == "D" else Sb)[(0,) + tuple(int(i) for i in idx[1:])] += sign * 1e-6
+            Ds.append(Db)
+            Ss.append(Sb)
+            gts.append(p.gt[b:b + 1])
+    print(f"[diff fd] {len(Ds)} oracle solves of {Y}x{X}x{nl}, {p.iters} iterations", flush=True)
+    ref = O.solve_potts(torch.from_numpy(np.concatenate(Ds)), torch.from_numpy(np.concatenate(Ss)),
+                        p.s_mode, p.c, p.tau, p.iters, p.ndim, history=False)["ell"]
+    g = torch.from_numpy(np.concatenate(gts).astype(np.int64))
+    f = -torch.gather(ref, 1, g.unsqueeze(1)).sum(dim=(1, 2, 3, 4)).numpy() / (B * Y * X)
+    worst = 0.0
+    for j, (which, idx) in enumerate(picks):
+        fd = (f[2 * j] - f[2 * j + 1]) / 2e-6
+        grad = gD if which == "D" else gS
+        scale = float(np.abs(grad[int(idx[0])]).max())
+        idx = tuple(int(i) for i in idx)
+        err = abs(float(grad[idx]) - fd) / scale
+        worst = max(worst, err)
+        print(f"[diff fd] {which}{idx}: gpu {float(grad[idx]):+.6e} "
+              f"fd {fd:+.6e} err/max {err:.1e}", flush=True)
+    assert worst <= 1e-3
+    # the boundary entries are where the loss depends on the inputs
+    assert sum(abs(f[2 * j] - f[2 * j + 1]) > 0 for j in range(16, 32)) >= 8
