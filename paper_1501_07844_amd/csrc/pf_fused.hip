@@ -111,23 +111,25 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
     const int zs = ch * g.cz;
     const int ze = min(a.nz, zs + g.cz);
 
-    // point A: owned voxel column (rows 0 .. FTY-1), or the halo row past
-    // the tile (row FTY); point B (row FTY+1): the column past the tile
-    const int xa = x0 + col, ya = y0 + row;
-    const bool va = row <= FTY && xa < a.nx && ya < a.ny;
+    // Each thread has one point: rows 0 .. FTY-1 an owned voxel column, row
+    // FTY the halo row past the tile, row FTY+1 (its own wavefronts) the
+    // column past the tile.  One set of carried registers serves either kind.
+    const bool colp = row == FTY + 1;
+    const int xa = colp ? x0 + FTX : x0 + col;
+    const int ya = colp ? y0 + col : y0 + row;
+    const bool va = (colp ? col < FTY : row <= FTY) && xa < a.nx && ya < a.ny;
     const bool own = row < FTY && va;
-    const int xb = x0 + FTX, yb = y0 + col;
-    const bool vb = row == FTY + 1 && col < FTY && xb < a.nx && yb < a.ny;
+    const int lr = colp ? col : row, lc = colp ? FTX : col;   // LDS slot of the point
 
     const size_t V = (size_t)a.V;
 
-    float ua[NLMAX], ub[NLMAX], er[NLMAX];   // er: unused here
-    float qa[NNMAX][ND], qb[NNMAX][ND];
+    float ua[NLMAX], er[NLMAX];   // er: unused here
+    float qa[NNMAX][ND];
     float qzb[NNMAX];
 #pragma unroll
     for (int A = 0; A < NNMAX; ++A) qzb[A] = 0.f;
 
-    // prologue: labels of plane zs (point A and B), old q_z of plane zs - 1
+    // prologue: labels of plane zs, old q_z of plane zs - 1
     if (va) {
         if (ND == 3 && zs > 0) {
             const int vbelow = ((zs - 1) * a.ny + ya) * a.nx + xa;
@@ -137,18 +139,7 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
         }
         label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xa, ya, zs, qzb, own, ua, qa, er);
 #pragma unroll
-        for (int L = 0; L < NLMAX; ++L) lds[L][row][col] = ua[L];
-    }
-    if (vb) {
-        if (ND == 3 && zs > 0) {
-            const int vbelow = ((zs - 1) * a.ny + yb) * a.nx + xb;
-#pragma unroll
-            for (int A = 0; A < NNMAX; ++A)
-                qzb[A] = ld_q<T, ND>(a.q_in, b, a.nn, A, ND - 1, V, (unsigned)vbelow);
-        }
-        label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xb, yb, zs, qzb, false, ub, qb, er);
-#pragma unroll
-        for (int L = 0; L < NLMAX; ++L) lds[L][col][FTX] = ub[L];
+        for (int L = 0; L < NLMAX; ++L) lds[L][lr][lc] = ua[L];
     }
     __syncthreads();
 
@@ -161,9 +152,9 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
 #pragma unroll
             for (int A = 0; A < NNMAX; ++A) sv[A] = smooth(a, b, A < a.nn ? A : a.nn - 1, v);
         }
-        float un[NLMAX], qn[NNMAX][ND], ubn[NLMAX];
+        float un[NLMAX], qn[NNMAX][ND];
 #pragma unroll
-        for (int L = 0; L < NLMAX; ++L) un[L] = ubn[L] = ua[L];   // defined when !has_next
+        for (int L = 0; L < NLMAX; ++L) un[L] = ua[L];   // defined when !has_next
         // labels of plane z + 1 (owned when z + 1 < ze, else the halo plane)
         if (va && has_next) {
             float qz[NNMAX];
@@ -171,12 +162,6 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
             for (int A = 0; A < NNMAX; ++A) qz[A] = qa[A][ND - 1];
             label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xa, ya, z + 1, qz, own && z + 1 < ze,
                                                     un, qn, er);
-        }
-        if (vb && has_next) {
-            float qz[NNMAX];
-#pragma unroll
-            for (int A = 0; A < NNMAX; ++A) qz[A] = qb[A][ND - 1];
-            label_point<ND, NLMAX, NNMAX, IDENT, T>(a, b, xb, yb, z + 1, qz, false, ubn, qb, er);
         }
         // flow step of the owned voxels of plane z
         if (own) {
@@ -210,22 +195,16 @@ __global__ __launch_bounds__(FTHREADS) void k_fused(StepArgs a, FusedGeom g) {
             }
         }
         __syncthreads();   // plane z of the LDS is no longer read
-        if (has_next) {
-            if (va) {
+        if (has_next && va) {
 #pragma unroll
-                for (int L = 0; L < NLMAX; ++L) {
-                    lds[L][row][col] = un[L];
-                    ua[L] = un[L];
-                }
-#pragma unroll
-                for (int A = 0; A < NNMAX; ++A)
-#pragma unroll
-                    for (int k = 0; k < ND; ++k) qa[A][k] = qn[A][k];
+            for (int L = 0; L < NLMAX; ++L) {
+                lds[L][lr][lc] = un[L];
+                ua[L] = un[L];
             }
-            if (vb) {
 #pragma unroll
-                for (int L = 0; L < NLMAX; ++L) lds[L][col][FTX] = ubn[L];
-            }
+            for (int A = 0; A < NNMAX; ++A)
+#pragma unroll
+                for (int k = 0; k < ND; ++k) qa[A][k] = qn[A][k];
         }
         __syncthreads();
     }
@@ -464,8 +443,16 @@ hipError_t fused_bucket(bool ident, int nl, int nn, F &f) {
         if (nl <= 8) return f.template operator()<ND, 8, 8, true, T>();
         return f.template operator()<ND, 16, 16, true, T>();
     }
+    // label graphs: the 3-D buckets of the two-pass kernels (up to 16 flows)
     if (nl <= 4 && nn <= 8) return f.template operator()<ND, 4, 8, false, T>();
+    if constexpr (ND == 3) {
+        if (nl <= 8 && nn <= 8) return f.template operator()<ND, 8, 8, false, T>();
+        if (nl <= 8 && nn <= 12) return f.template operator()<ND, 8, 12, false, T>();
+    }
     if (nl <= 8 && nn <= 16) return f.template operator()<ND, 8, 16, false, T>();
+    if constexpr (ND == 3) {
+        if (nl <= 12 && nn <= 16) return f.template operator()<ND, 12, 16, false, T>();
+    }
     return f.template operator()<ND, 16, 16, false, T>();
 }
 

@@ -117,9 +117,10 @@ hipError_t launch_flow(const StepArgs &a, bool ident, int nd, int st, hipStream_
 hipError_t launch_fused(const StepArgs &a, bool ident, int nd, int st, hipStream_t) {
     const FusedGeom g = fused_geometry(a);
     auto f = [&]<int ND, int NL, int NN, bool ID, typename T>() {
-        // the fused build: (4, 8), (8, 16), (16, 16) for label graphs
-        constexpr int NL2 = (NL > 8 ? 16 : NL);
-        constexpr int NN2 = ID ? NN : (NL2 == 4 ? 8 : 16);
+        // the fused builds for label graphs: the two-pass buckets in 3-D,
+        // (4, 8), (8, 16), (16, 16) in 2-D
+        constexpr int NL2 = (ID || ND == 3) ? NL : (NL > 8 ? 16 : NL);
+        constexpr int NN2 = (ID || ND == 3) ? NN : (NL2 == 4 ? 8 : 16);
         run_grid(dim3((unsigned)g.blocks), FTHREADS, true, [&] { k_fused<ND, NL2, NN2, ID, T>(a, g); });
         return 0;
     };
