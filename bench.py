@@ -13,7 +13,8 @@ x non-source label nodes) of the headline solve; the roofline of its kernel
 the timed region; the per-iteration kernel rates of every workload (Potts 3-D, HMF, DAGMF and an
 Ishikawa chain scaled to 128 x 256 x 256 with 8 ordered labels; float32, bf16
 and fp16 state), whole-solve rates of the two small 2-D cases (Potts and
-Ishikawa); a plain device copy as the achievable bandwidth;
+Ishikawa) and of a batch of 256 of the Potts case (LDS-resident solve against
+the two-pass kernels); a plain device copy as the achievable bandwidth;
 the cost of the differentiable solve; and the float64 reference
 implementation timed on a bounded sample on the host.
 
@@ -248,6 +249,42 @@ def potts2d_leg(dev, reps: int = 5) -> dict:
             "energy": r.energy, "gap": r.gap}
 
 
+def potts2d_batch_leg(dev, batch: int = 256, reps: int = 5) -> dict:
+    """A batch of `batch` copies of the 64 x 64 Potts case (3 labels, 200
+    iterations): the kernel AUTO takes (the LDS-resident solve, one compute
+    unit per problem) against the forced two-pass kernels, whole batch
+    solves per second, median of `reps`, and the two solutions compared."""
+    import numpy as np
+    import torch
+
+    import paper_1501_07844_amd as pf
+    from paper_1501_07844_amd import synth
+    p = synth.potts2d_rects()
+    _, S = _inputs(p, dev)                       # node constants: the same for every copy
+    D = torch.from_numpy(np.ascontiguousarray(np.repeat(p.D, batch, axis=0))).to(dev)
+    out = {"workload": f"potts2d_rects 64x64 x{batch}, 3 labels, 200 iterations, fp32"}
+    sols = {}
+    for name, kernel in (("auto", "auto"), ("two_pass", "two_pass")):
+        kw = dict(c=p.c, tau=p.tau, iters=p.iters, s_mode=p.s_mode, ndim=2, kernel=kernel,
+                  final_energy=False, return_labels=False)
+        r = pf.solve_potts(D, S, **kw)
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = pf.solve_potts(D, S, workspace=r.workspace, **kw)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        t = sorted(ts)[len(ts) // 2]
+        sols[name] = r.u
+        out[name] = {"ms_per_solve": round(1e3 * t, 3),
+                     "voxel_label_its_per_s": batch * p.voxels * p.n_node * p.iters / t}
+    out["auto"]["kernel"] = pf.auto_kernel((batch,) + tuple(p.shape[1:]), p.n_leaf, p.n_node, 2)
+    out["speedup_vs_two_pass"] = round(out["two_pass"]["ms_per_solve"] / out["auto"]["ms_per_solve"], 3)
+    out["same_u_bitwise"] = bool(torch.equal(sols["auto"], sols["two_pass"]))
+    return out
+
+
 def ishikawa2d_leg(dev, reps: int = 5) -> dict:
     """The ordered-label workload at its own size (96 x 128, 5 levels, 200
     iterations): whole solves per second, median of `reps`."""
@@ -424,6 +461,8 @@ def main() -> int:
                     abs(legs[i + j]["energy_full"] - legs[i]["energy_full"]) / abs(legs[i]["energy_full"]))
         out["workloads"] = legs
         out["potts2d"] = potts2d_leg(dev)
+        out["potts2d_batch"] = potts2d_batch_leg(dev)
+        torch.cuda.empty_cache()
         out["ishikawa2d"] = ishikawa2d_leg(dev)
 
     if not args.no_adjoint:

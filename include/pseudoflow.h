@@ -67,15 +67,22 @@ typedef enum {
 } pf_s_mode;
 
 typedef enum {
-    PF_KERNEL_AUTO = 0,      /* the faster variant as measured on MI355X: for 3-D Potts
+    PF_KERNEL_AUTO = 0,      /* the faster variant as measured on MI355X: LDS for
+                                batches of 8 or more 2-D problems whose state fits in
+                                LDS; for 3-D Potts
                                 FUSED2 up to 8 labels (every storage type), beyond
                                 that FUSED with fp32 state; two-pass otherwise */
     PF_KERNEL_TWO_PASS = 1,  /* label pass then flow pass, state updated in place */
     PF_KERNEL_FUSED = 2,     /* one pass per iteration, state ping-ponged */
-    PF_KERNEL_FUSED2 = 3     /* one pass per two iterations (3-D Potts, n_leaf <= 8;
+    PF_KERNEL_FUSED2 = 3,    /* one pass per two iterations (3-D Potts, n_leaf <= 8;
                                 PF_EUNSUPPORTED otherwise), state ping-ponged; an
                                 iteration that ends on a gap check, or the last of an
                                 odd count, runs the one-iteration pass */
+    PF_KERNEL_LDS = 4        /* 2-D problems of at most 4096 voxels, 8 leaves and 16
+                                flows whose float32 state, n_leaf + 2 n_node floats
+                                per voxel, fits in 160 KB of LDS: one launch runs
+                                every iteration up to the next gap check, one block
+                                per problem (PF_EUNSUPPORTED otherwise) */
 } pf_kernel;
 
 typedef struct {
@@ -103,7 +110,8 @@ typedef struct {
     int32_t check_inputs;    /* 1: reject NaN/Inf in D and NaN/Inf/negative S first */
     int32_t timing_stride;   /* > 0: time the launch starting every timing_stride-th
                                 iteration with HIP events (one launch covers two
-                                iterations with PF_KERNEL_FUSED2) */
+                                iterations with PF_KERNEL_FUSED2; with PF_KERNEL_LDS
+                                every launch is timed) */
     void *workspace;         /* device, 256-byte aligned, caller-owned */
     size_t workspace_bytes;
     /* Differentiable solves (float32 state only).  With tape != NULL the
@@ -145,8 +153,8 @@ size_t pf_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t n_node,
 /* The kernel PF_KERNEL_AUTO runs for an unrecorded solve of this problem:
  * identity != 0 for the Potts model, 0 for a label graph (the Ishikawa chain
  * always runs PF_KERNEL_TWO_PASS); storage is a pf_storage.  Host only, no
- * device work.  Returns PF_KERNEL_TWO_PASS, PF_KERNEL_FUSED or
- * PF_KERNEL_FUSED2, or -1 for arguments no solver accepts. */
+ * device work.  Returns PF_KERNEL_TWO_PASS, PF_KERNEL_FUSED, PF_KERNEL_FUSED2
+ * or PF_KERNEL_LDS, or -1 for arguments no solver accepts. */
 int32_t pf_auto_kernel(const pf_grid *grid, int32_t n_leaf, int32_t n_node, int32_t identity,
                        int32_t storage);
 
@@ -180,7 +188,8 @@ int solve_hmf(const pf_grid *grid, const pf_graph *graph, const float *D, const 
 /* Pseudo-flow Ishikawa chain (Algorithm 3): labels L_0..L_N (n_labels = N+1),
  * flows q_1..q_N; flow excess d_i = D_i + sum_{j<=i} div q_j and the flow of
  * L_i driven by U_i = sum_{j>=i} u_j.  D: device float[B][N+1][Z][Y][X];
- * S per s_mode with n_node = N.  Supports PF_KERNEL_TWO_PASS/AUTO. */
+ * S per s_mode with n_node = N.  Supports PF_KERNEL_TWO_PASS, PF_KERNEL_LDS
+ * and AUTO (LDS for batches of 8 or more problems that fit, else two-pass). */
 int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
                    int32_t s_mode, const pf_params *params, pf_result *result, void *stream);
 
@@ -207,8 +216,8 @@ size_t pf_backward_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t 
  * the reverse step: PF_KERNEL_TWO_PASS runs two kernels (projection adjoint,
  * then label adjoint), PF_KERNEL_FUSED one fused kernel (PF_EUNSUPPORTED
  * beyond 8 Potts labels in 2-D, 4 in 3-D, or 4 leaves / 8 flows on a 2-D
- * label graph; not for 3-D label graphs), PF_KERNEL_FUSED2 PF_EUNSUPPORTED,
- * PF_KERNEL_AUTO the two kernels
+ * label graph; not for 3-D label graphs), PF_KERNEL_FUSED2 and
+ * PF_KERNEL_LDS PF_EUNSUPPORTED, PF_KERNEL_AUTO the two kernels
  * (faster on MI355X).  Both give the same gradients bit for bit.  The tape
  * and the inputs must be those of the recorded call: the library cannot
  * check that.  Calls sharing a workspace must not overlap. */

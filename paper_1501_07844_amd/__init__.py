@@ -32,7 +32,7 @@ __all__ = [
 PF_OK, PF_EINVAL, PF_EGRAPH, PF_ENOMEM, PF_EHIP, PF_ENONFINITE, PF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MAX_LEAVES, MAX_NODES = 16, 32
 STORAGE = {"fp32": 0, "bf16": 1, "fp16": 2}
-KERNEL = {"auto": 0, "two_pass": 1, "fused": 2, "fused2": 3}
+KERNEL = {"auto": 0, "two_pass": 1, "fused": 2, "fused2": 3, "lds": 4}
 S_MODE = {"node_scalar": 0, "shared_field": 1, "node_field": 2}
 
 # every symbol include/pseudoflow.h declares
@@ -186,7 +186,7 @@ def workspace_bytes(shape, n_leaf: int, n_node: int, ndim: int, storage: str = "
 def auto_kernel(shape, n_leaf: int, n_node: int, ndim: int, storage: str = "fp32",
                 identity: bool = True) -> str:
     """The kernel ``kernel="auto"`` runs for an unrecorded solve of a
-    [B, Z, Y, X] problem ("two_pass", "fused" or "fused2")."""
+    [B, Z, Y, X] problem ("two_pass", "fused", "fused2" or "lds")."""
     B, Z, Y, X = shape
     k = int(library().pf_auto_kernel(C.byref(_Grid(B, ndim, Z, Y, X)), n_leaf, n_node,
                                      int(bool(identity)), STORAGE[storage]))
@@ -295,8 +295,9 @@ def solve_potts(D, S, *, c: float, tau: float, iters: int, **kw) -> SolveResult:
     S: scalar or host sequence of n per-label constants, or a device field
     [B][Z][Y][X] (shared) or [B][n][Z][Y][X] (per label).  ``kernel``:
     "auto" (see ``auto_kernel``), "two_pass", "fused" (one pass per
-    iteration) or "fused2" (one pass per two iterations; 3-D, n <= 8); all
-    give the same result bit for bit."""
+    iteration), "fused2" (one pass per two iterations; 3-D, n <= 8) or
+    "lds" (2-D problems whose state fits in LDS: every iteration up to the
+    next gap check in one launch); all give the same result bit for bit."""
     n = int(D.shape[1])
     return _solve(library().solve_potts, D, S, n, n, n_labels=n, c=c, tau=tau, iters=iters, **kw)
 

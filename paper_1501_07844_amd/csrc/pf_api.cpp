@@ -134,7 +134,7 @@ int check_params(const pf_params *P) {
         return fail(PF_EINVAL, "tau must be finite and > 0");
     if (P->storage < PF_FP32 || P->storage > PF_FP16)
         return fail(PF_EINVAL, "unknown storage %d", P->storage);
-    if (P->kernel < PF_KERNEL_AUTO || P->kernel > PF_KERNEL_FUSED2)
+    if (P->kernel < PF_KERNEL_AUTO || P->kernel > PF_KERNEL_LDS)
         return fail(PF_EINVAL, "unknown kernel %d", P->kernel);
     if (P->gap_every < 0) return fail(PF_EINVAL, "gap_every must be >= 0");
     if (!(P->gap_tol >= 0.0)) return fail(PF_EINVAL, "gap_tol must be >= 0");
@@ -270,12 +270,19 @@ int check_tape(const Prob &p, const pf_params *P) {
 int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
     int tst = check_tape(p, P);
     if (tst != PF_OK) return tst;
-    if (P->tape && (P->kernel == PF_KERNEL_FUSED || P->kernel == PF_KERNEL_FUSED2))
+    if (P->tape && (P->kernel == PF_KERNEL_FUSED || P->kernel == PF_KERNEL_FUSED2 ||
+                    P->kernel == PF_KERNEL_LDS))
         return fail(PF_EUNSUPPORTED, "a recorded solve uses the two-pass kernels");
-    const bool want_fused2 = !P->tape && (P->kernel == PF_KERNEL_FUSED2 ||
+    const long V = (long)p.g.nx * p.g.ny * p.g.nz;
+    const bool want_lds = !P->tape && (P->kernel == PF_KERNEL_LDS ||
+                          (P->kernel == PF_KERNEL_AUTO &&
+                           lds_preferred(p.g.ndim, p.nl, p.nn, V, p.g.batch)));
+    if (want_lds && !lds_supported(p.g.ndim, p.nl, p.nn, V))
+        return fail(PF_EUNSUPPORTED, "the state of one problem does not fit in LDS");
+    const bool want_fused2 = !P->tape && !want_lds && (P->kernel == PF_KERNEL_FUSED2 ||
                              (P->kernel == PF_KERNEL_AUTO &&
                               fused2_preferred(p.g.ndim, p.nl, p.nn, p.ident, P->storage)));
-    const bool want_fused = want_fused2 || (!P->tape && (P->kernel == PF_KERNEL_FUSED ||
+    const bool want_fused = want_fused2 || (!P->tape && !want_lds && (P->kernel == PF_KERNEL_FUSED ||
                             (P->kernel == PF_KERNEL_AUTO &&
                              fused_preferred(p.g.ndim, p.nl, p.nn, p.ident, P->storage))));
     if (P->kernel == PF_KERNEL_FUSED && !fused_supported(p.g.ndim, p.nl, p.nn, p.ident))
@@ -378,7 +385,11 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
         // two iterations in one pass unless a gap check falls after the first
         const bool pair = want_fused2 && it + 1 < P->iters &&
                           !(P->gap_every > 0 && (it + 1) % P->gap_every == 0);
-        const int step = pair ? 2 : 1;
+        // the LDS kernel runs every iteration up to the next gap check
+        const int step = want_lds ? (P->gap_every > 0 ? std::min(P->iters - it,
+                                                                  P->gap_every - it % P->gap_every)
+                                                      : P->iters - it)
+                                  : pair ? 2 : 1;
         if (P->tape && it % P->ckpt_every == 0) {
             char *slot = static_cast<char *>(P->tape) + (size_t)(it / P->ckpt_every) * tg.slot_bytes;
             if ((e = launch_copy_f(static_cast<const float *>(ell[0]), reinterpret_cast<float *>(slot),
@@ -387,7 +398,7 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
                                    reinterpret_cast<float *>(slot + tg.ell_bytes), n_q, stream)) != hipSuccess)
                 return hip_fail(e, "checkpoint");
         }
-        const bool timed = P->timing_stride > 0 && it % P->timing_stride == 0;
+        const bool timed = P->timing_stride > 0 && (want_lds || it % P->timing_stride == 0);
         if (timed) {
             hipEvent_t e0, e1;
             if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -396,7 +407,10 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
             timer.ev.push_back(e1);
             hipEventRecord(e0, stream);
         }
-        if (want_fused) {
+        if (want_lds) {
+            if ((e = launch_lds(a, ident, P->storage, step, stream)) != hipSuccess)
+                return hip_fail(e, "LDS-resident iterations");
+        } else if (want_fused) {
             a.ell_in = ell[cur];
             a.q_in = q[cur];
             a.ell_out = ell[1 - cur];
@@ -549,6 +563,7 @@ int run_backward(Prob &p, const pf_params *P, const float *grad_ell, float *grad
     // fused one holds one tile per compute unit at its register count)
     if (P->kernel == PF_KERNEL_FUSED2)
         return fail(PF_EUNSUPPORTED, "no two-iteration reverse kernel");
+    if (P->kernel == PF_KERNEL_LDS) return fail(PF_EUNSUPPORTED, "no LDS-resident reverse kernel");
     const bool fused = P->kernel == PF_KERNEL_FUSED;
     if (fused && !adj_fused_supported(nd, p.nl, p.nn, p.ident))
         return fail(PF_EUNSUPPORTED, "fused reverse kernel unavailable for this problem");
@@ -680,6 +695,8 @@ int32_t pf_auto_kernel(const pf_grid *grid, int32_t n_leaf, int32_t n_node, int3
     if (storage < PF_FP32 || storage > PF_FP16) return -1;
     const bool id = identity != 0;
     if (id && n_node != n_leaf) return -1;
+    if (lds_preferred(grid->ndim, n_leaf, n_node, (long)grid->nx * grid->ny * grid->nz, grid->batch))
+        return PF_KERNEL_LDS;
     if (fused2_preferred(grid->ndim, n_leaf, n_node, id, storage)) return PF_KERNEL_FUSED2;
     if (fused_preferred(grid->ndim, n_leaf, n_node, id, storage)) return PF_KERNEL_FUSED;
     return PF_KERNEL_TWO_PASS;
@@ -789,7 +806,9 @@ int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const 
         for (int L = j + 1; L < p.nl; ++L) p.w.w[j][L] = 1.0f;
     if ((st = check_inputs_common(p, D, S, s_mode)) != PF_OK) return st;
     pf_params P2 = *params;
-    P2.kernel = PF_KERNEL_TWO_PASS;
+    if (P2.kernel == PF_KERNEL_AUTO)
+        P2.kernel = lds_preferred(p.g.ndim, p.nl, p.nn, (long)p.g.nx * p.g.ny * p.g.nz, p.g.batch)
+                        ? PF_KERNEL_LDS : PF_KERNEL_TWO_PASS;
     return run(p, &P2, result, static_cast<hipStream_t>(stream));
 }
 

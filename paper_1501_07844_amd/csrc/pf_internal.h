@@ -103,6 +103,14 @@ hipError_t launch_upload(const ConstBlock &c, float *dst, hipStream_t s);
 hipError_t launch_init(const StepArgs &a, int nd, int storage, float ell0, hipStream_t s);
 hipError_t launch_label(const StepArgs &a, bool ident, int nd, int storage, hipStream_t s);
 hipError_t launch_flow(const StepArgs &a, bool ident, int nd, int storage, hipStream_t s);
+// whole 2-D problems in LDS: `iters` iterations per launch, one block per
+// problem, state in place
+constexpr int kLdsThreads = 1024;
+constexpr int kLdsVox = 4;              // voxels per thread (V <= 4096)
+constexpr int kLdsFloats = 40 * 1024;   // 160 KB of LDS per block
+bool lds_supported(int nd, int nl, int nn, long V);
+bool lds_preferred(int nd, int nl, int nn, long V, int batch);
+hipError_t launch_lds(const StepArgs &a, bool ident, int storage, int iters, hipStream_t s);
 hipError_t launch_fused(const StepArgs &a, bool ident, int nd, int storage, hipStream_t s);
 bool fused_supported(int nd, int nl, int nn, bool identity);
 bool fused_preferred(int nd, int nl, int nn, bool identity, int storage);

@@ -133,6 +133,142 @@ __global__ __launch_bounds__(kBlock) void k_flow(StepArgs a) {
     flow_body<ND, NLMAX, NNMAX, IDENT, T>(a);
 }
 
+// --------------------------------------------- LDS-resident 2-D solve ----
+// A 2-D problem whose float32 state fits in one compute unit's LDS (the
+// 64 x 64 image with 3 labels: 147 KB) runs many iterations per launch: one
+// block per problem loads ell and q into LDS, performs the label pass and
+// the flow pass of every iteration there (a barrier after each), and stores
+// the state back.  Each thread has up to kLdsVox voxels (the loops over them
+// are unrolled, so their LDS reads overlap) and keeps their data terms in
+// registers for the whole launch, so no global load waits inside the
+// iterations but the capacities'.  LDS holds each value as the storage type
+// holds it (every store goes through the same rounding) and each voxel's
+// expressions are those of label_body / flow_body, so the result equals the
+// two-pass kernels' bit for bit; at this size those are bound by launch
+// latency (two launches per iteration, a few thousand voxels each).
+template <int NLMAX, int NNMAX, bool IDENT, typename T>
+__global__ __launch_bounds__(kLdsThreads) void k_lds2d(StepArgs a, int iters) {
+    __shared__ float sm[kLdsFloats];
+    const int b = blockIdx.x;
+    const int V = a.V;
+    const size_t Vs = (size_t)V;
+    float *se = sm;                          // ell [nl][V]
+    float *sq = sm + (size_t)a.nl * V;       // q [nn][2][V]
+    const T *Tn = nullptr;
+    float dr[kLdsVox][NLMAX];                // data terms of the thread's voxels
+    int cx[kLdsVox], cy[kLdsVox];            // and their coordinates
+#pragma unroll
+    for (int j = 0; j < kLdsVox; ++j) {
+        const int v = threadIdx.x + j * kLdsThreads;
+        const unsigned vc = (unsigned)(v < V ? v : V - 1);
+        cx[j] = (int)vc % a.nx;
+        cy[j] = (int)vc / a.nx;
+#pragma unroll
+        for (int L = 0; L < NLMAX; ++L)
+            dr[j][L] = ldf(field<float>(a.D, b, a.nl, L < a.nl ? L : a.nl - 1, Vs), vc);
+        if (v < V) {
+            for (int L = 0; L < a.nl; ++L) se[L * V + v] = ld_ell<T>(a.ell_in, b, a.nl, L, Vs, (unsigned)v);
+            for (int A = 0; A < a.nn; ++A)
+                for (int k = 0; k < 2; ++k)
+                    sq[(A * 2 + k) * V + v] = ld_q<T, 2>(a.q_in, b, a.nn, A, k, Vs, (unsigned)v);
+        }
+    }
+    __syncthreads();
+    for (int it = 0; it < iters; ++it) {
+        // label pass (label_body).  The voxel index is made opaque per
+        // iteration so that the LDS addresses derived from it are formed
+        // where they are used instead of being kept live across iterations.
+#pragma unroll
+        for (int j = 0; j < kLdsVox; ++j) {
+            if (threadIdx.x + j * kLdsThreads < V) {
+                int v = cy[j] * a.nx + cx[j];
+                __asm__ volatile("" : "+v"(v));
+                const Coord c{cx[j], cy[j], 0};
+                int m[3];
+                bool bwd[3];
+                backward_offsets(c, a, m, bwd);
+                const bool fwd[3] = {c.x < a.nx - 1, c.y < a.ny - 1, false};
+                float d[NLMAX], e[NLMAX], q0[NNMAX][3], qm[NNMAX][3];
+#pragma unroll
+                for (int L = 0; L < NLMAX; ++L) {
+                    d[L] = dr[j][L];
+                    e[L] = se[(L < a.nl ? L : a.nl - 1) * V + v];
+                }
+#pragma unroll
+                for (int A = 0; A < NNMAX; ++A) {
+                    const int Ac = A < a.nn ? A : a.nn - 1;
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) {
+                        q0[A][k] = sq[(Ac * 2 + k) * V + v];
+                        qm[A][k] = sq[(Ac * 2 + k) * V + v - m[k]];
+                    }
+                }
+#pragma unroll
+                for (int A = 0; A < NNMAX; ++A)
+                    add_excess<NLMAX, IDENT>(a, d, A, div_from<2>(q0[A], qm[A], fwd, bwd));
+                entropic_step<NLMAX>(a, d, e);
+#pragma unroll
+                for (int L = 0; L < NLMAX; ++L)
+                    if (L < a.nl) se[L * V + v] = roundtrip(e[L], Tn);
+            }
+        }
+        __syncthreads();
+        // flow pass (flow_body)
+#pragma unroll
+        for (int j = 0; j < kLdsVox; ++j) {
+            if (threadIdx.x + j * kLdsThreads < V) {
+                int v = cy[j] * a.nx + cx[j];
+                __asm__ volatile("" : "+v"(v));
+                const Coord c{cx[j], cy[j], 0};
+                const bool h[3] = {c.x < a.nx - 1, c.y < a.ny - 1, false};
+                const int off[2] = {h[0] ? 1 : 0, h[1] ? a.nx : 0};
+                float gu[NLMAX][2];
+#pragma unroll
+                for (int L = 0; L < NLMAX; ++L) {
+                    const int Lc = L < a.nl ? L : a.nl - 1;
+                    const float u0 = __expf(se[Lc * V + v]);
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) gu[L][k] = h[k] ? __expf(se[Lc * V + v + off[k]]) - u0 : 0.f;
+                }
+#pragma unroll
+                for (int A = 0; A < NNMAX; ++A) {
+                    if (A < a.nn) {
+                        const float qv[2] = {sq[(A * 2) * V + v], sq[(A * 2 + 1) * V + v]};
+                        float G[3], p[2];
+                        grad_U<2, NLMAX, IDENT>(a, A, gu, G);
+                        flow_project<2>(a, qv, G, h, smooth(a, b, A, v), p);
+                        sq[(A * 2) * V + v] = roundtrip(p[0], Tn);
+                        sq[(A * 2 + 1) * V + v] = roundtrip(p[1], Tn);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int v = threadIdx.x; v < V; v += kLdsThreads) {
+        for (int L = 0; L < a.nl; L += 2)
+            st_ell2<T>(a.ell_out, b, a.nl, L, Vs, (unsigned)v, se[L * V + v],
+                       L + 1 < a.nl ? se[(L + 1) * V + v] : 0.f);
+        for (int A = 0; A < a.nn; A += 2)
+            for (int k = 0; k < 2; ++k)
+                st_q2<T, 2>(a.q_out, b, a.nn, A, k, Vs, (unsigned)v, sq[(A * 2 + k) * V + v],
+                            A + 1 < a.nn ? sq[((A + 1) * 2 + k) * V + v] : 0.f);
+    }
+}
+
+// the builds of the LDS-resident solve (up to 8 leaves and 16 flows)
+template <typename T, typename F>
+hipError_t lds_bucket(bool ident, int nl, int nn, F &f) {
+    if (ident) {
+        if (nl <= 4) return f.template operator()<4, 4, true, T>();
+        return f.template operator()<8, 8, true, T>();
+    }
+    if (nl <= 4 && nn <= 8) return f.template operator()<4, 8, false, T>();
+    if (nl <= 8 && nn <= 8) return f.template operator()<8, 8, false, T>();
+    if (nl <= 8 && nn <= 12) return f.template operator()<8, 12, false, T>();
+    return f.template operator()<8, 16, false, T>();
+}
+
 // ------------------------------------------------- init / copy / export --
 
 template <typename T>
@@ -461,6 +597,31 @@ hipError_t launch_copy_state(const StepArgs &a, int nd, int storage, hipStream_t
 hipError_t launch_upload(const ConstBlock &c, float *dst, hipStream_t s) {
     k_upload<<<(kConstFloats + kBlock - 1) / kBlock, kBlock, 0, s>>>(c, dst);
     return hipGetLastError();
+}
+
+bool lds_supported(int nd, int nl, int nn, long V) {
+    return nd == 2 && nl <= 8 && nn <= 16 && V > 0 && V <= (long)kLdsVox * kLdsThreads &&
+           V * (long)(nl + 2 * nn) <= kLdsFloats;
+}
+
+// PF_KERNEL_AUTO takes the LDS-resident solve from 8 problems up: one compute
+// unit per problem and no HBM traffic per iteration (64 x 64, 3 labels, 200
+// iterations: batch 256 1.55 against 4.5 ms for the two-pass kernels, batch
+// 8 1.53 against 1.59 ms); a single problem runs on one compute unit and is
+// no faster than the two-pass kernels' launches (1.52 against 1.49 ms).
+bool lds_preferred(int nd, int nl, int nn, long V, int batch) {
+    return batch >= 8 && lds_supported(nd, nl, nn, V);
+}
+
+hipError_t launch_lds(const StepArgs &a, bool ident, int storage, int iters, hipStream_t s) {
+    if (!lds_supported(2, a.nl, a.nn, a.V) || a.nz != 1 || iters < 1) return hipErrorInvalidValue;
+    return dispatch_type(storage, [&]<typename T>() {
+        auto go = [&]<int NL, int NN, bool ID, typename U>() {
+            k_lds2d<NL, NN, ID, U><<<(unsigned)a.B, kLdsThreads, 0, s>>>(a, iters);
+            return hipGetLastError();
+        };
+        return lds_bucket<T>(ident, a.nl, a.nn, go);
+    });
 }
 
 hipError_t launch_label(const StepArgs &a, bool ident, int nd, int storage, hipStream_t s) {

@@ -10,7 +10,7 @@ AddressSanitizer and UBSan, driven through the C ABI with host buffers.
    reference implementation, and the fused reverse step bit for bit against
    the two-kernel one.
 
-Usage: python check.py path/to/libcpu.so [forward] [fused2] [reverse]
+Usage: python check.py path/to/libcpu.so [forward] [fused2] [lds] [reverse]
 """
 import ctypes as C
 import os
@@ -96,6 +96,29 @@ def check_forward():
             b = solve(p, iters, "fused", storage)
             same = all(np.array_equal(x, y) for x, y in zip(a[:2], b[:2])) and a[3:] == b[3:]
             print(f"forward {name:24s} {storage}: fused == two-pass bitwise: {same}", flush=True)
+            bad += not same
+    return bad
+
+
+def lds_cases():
+    rng = np.random.default_rng(9)
+    dag = synth.random_dag(rng, 3, 5)
+    return [
+        ("potts2d nl3 64x64", synth.potts2d_rects(), 9, 0),
+        ("potts2d nl5 B2 nodefield", synth.random_potts(7, (1, 37, 70), 2, 5, batch=2, s_mode="node_field"), 8, 3),
+        ("dag2d nl5 nn8 shared", synth.random_problem(8, (1, 26, 37), 2, dag, s_mode="shared_field"), 6, 4),
+    ]
+
+
+def check_lds():
+    """The LDS-resident 2-D solve against the two-pass kernels."""
+    bad = 0
+    for name, p, iters, gap_every in lds_cases():
+        for storage in ("fp32", "bf16", "fp16"):
+            a = solve(p, iters, "two_pass", storage, gap_every=gap_every)
+            b = solve(p, iters, "lds", storage, gap_every=gap_every)
+            same = all(np.array_equal(x, y) for x, y in zip(a[:2], b[:2])) and a[3:] == b[3:]
+            print(f"forward {name:24s} {storage}: LDS-resident == two-pass bitwise: {same}", flush=True)
             bad += not same
     return bad
 
@@ -214,6 +237,8 @@ if __name__ == "__main__":
         n_bad += check_forward()
     if not only or "fused2" in only:
         n_bad += check_fused2()
+    if not only or "lds" in only:
+        n_bad += check_lds()
     if not only or "reverse" in only:
         n_bad += check_reverse()
     print("ALL OK" if n_bad == 0 else f"{n_bad} FAILED")

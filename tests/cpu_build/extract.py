@@ -20,7 +20,9 @@ def cut(text, start_marker, end_marker):
 
 def main(out):
     os.makedirs(out, exist_ok=True)
-    k = open(os.path.join(SRC, "pf_kernels.hip")).read()
+    # the empty asm that hides a value from the optimiser names a VGPR operand
+    k = open(os.path.join(SRC, "pf_kernels.hip")).read().replace(
+        '__asm__ volatile("" : "+v"(v));', '__asm__ volatile("" : "+r"(v));')
     k = k[:k.index("// ----------------------------------------------------------- dispatch ----")]
     k += "\n}  // namespace\n}  // namespace pf\n"
     f = open(os.path.join(SRC, "pf_fused.hip")).read()

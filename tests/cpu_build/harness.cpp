@@ -114,6 +114,13 @@ hipError_t launch_flow(const StepArgs &a, bool ident, int nd, int st, hipStream_
         return 0;
     });
 }
+hipError_t launch_lds(const StepArgs &a, bool ident, int st, int iters, hipStream_t) {
+    if (!lds_supported(2, a.nl, a.nn, a.V) || a.nz != 1 || iters < 1) return 1;
+    return disp(2, st, ident, a.nl, a.nn, [&]<int ND, int NL, int NN, bool ID, typename T>() {
+        run_grid(dim3((unsigned)a.B), kLdsThreads, true, [&] { k_lds2d<NL, NN, ID, T>(a, iters); });
+        return 0;
+    });
+}
 hipError_t launch_fused(const StepArgs &a, bool ident, int nd, int st, hipStream_t) {
     const FusedGeom g = fused_geometry(a);
     auto f = [&]<int ND, int NL, int NN, bool ID, typename T>() {

@@ -61,10 +61,13 @@ def _params(**kw):
 
 
 def test_auto_kernel_choice():
-    """The kernel AUTO resolves to: two iterations per pass for 3-D Potts
-    up to 8 labels in every storage type, the one-iteration fused pass
-    beyond with float32 state, the two-pass kernels for 16-bit state beyond
-    8 labels, 2-D problems and label graphs."""
+    """The kernel AUTO resolves to: the LDS-resident solve for batches of 8
+    or more 2-D problems of at most 4096 voxels, 8 leaves and 16 flows whose
+    float32 state (n_leaf + 2 n_node floats per voxel) fits in 160 KB;
+    two iterations per pass for 3-D Potts up to 8 labels in every storage
+    type, the one-iteration fused pass beyond with float32 state, the
+    two-pass kernels for 16-bit state beyond 8 labels, larger 2-D problems
+    and 3-D label graphs."""
     k = pf.KERNEL
     assert pf.auto_kernel((1, 256, 256, 256), 8, 8, 3) == "fused2"
     assert pf.auto_kernel((2, 5, 7, 9), 3, 3, 3) == "fused2"
@@ -73,6 +76,15 @@ def test_auto_kernel_choice():
     assert pf.auto_kernel((1, 16, 16, 16), 8, 8, 3, "fp16") == "fused2"
     assert pf.auto_kernel((1, 16, 16, 16), 12, 12, 3, "bf16") == "two_pass"
     assert pf.auto_kernel((1, 1, 64, 64), 8, 8, 2) == "two_pass"
+    assert pf.auto_kernel((8, 1, 64, 64), 3, 3, 2) == "lds"                 # 36864 of 40960 floats
+    assert pf.auto_kernel((1, 1, 64, 64), 3, 3, 2) == "two_pass"            # a single problem
+    assert pf.auto_kernel((7, 1, 64, 64), 3, 3, 2) == "two_pass"
+    assert pf.auto_kernel((16, 1, 40, 52), 5, 4, 2, identity=False) == "lds"
+    assert pf.auto_kernel((8, 1, 64, 64), 4, 4, 2) == "two_pass"            # 49152 floats > 40960
+    assert pf.auto_kernel((8, 1, 52, 64), 4, 4, 2) == "lds"                 # 39936 floats
+    assert pf.auto_kernel((8, 1, 64, 65), 3, 3, 2) == "two_pass"            # 4160 voxels > 4096
+    assert pf.auto_kernel((8, 1, 64, 64), 5, 5, 2) == "two_pass"            # 61440 floats > 40960
+    assert pf.auto_kernel((8, 1, 40, 40), 9, 9, 2) == "two_pass"            # more than 8 labels
     assert pf.auto_kernel((1, 16, 16, 16), 8, 11, 3, identity=False) == "two_pass"
     lib = pf.library()
     assert lib.pf_auto_kernel(C.byref(_grid()), 4, 5, 1, 0) == -1          # Potts needs n_node == n_leaf
@@ -167,6 +179,8 @@ DEV = 1 << 20          # fake aligned pointers
     ("null_params", pf.PF_EINVAL), ("bad_kernel", pf.PF_EINVAL),
     ("fused2_2d", pf.PF_EUNSUPPORTED), ("fused2_9_labels", pf.PF_EUNSUPPORTED),
     ("fused2_recorded", pf.PF_EUNSUPPORTED), ("too_many_voxels", pf.PF_EUNSUPPORTED),
+    ("lds_3d", pf.PF_EUNSUPPORTED), ("lds_too_big", pf.PF_EUNSUPPORTED),
+    ("lds_recorded", pf.PF_EUNSUPPORTED),
 ])
 def test_potts_argument_errors(case, code):
     g, n, D, S, mode, p = _grid(), 3, DEV, SADDR, 0, _params()
@@ -209,7 +223,16 @@ def test_potts_argument_errors(case, code):
     elif case == "null_params":
         p = None
     elif case == "bad_kernel":
-        p.kernel = 4
+        p.kernel = 5
+    elif case == "lds_3d":
+        p.kernel = pf.KERNEL["lds"]
+    elif case == "lds_too_big":
+        g = _grid(1, 2, 1, 64, 80)            # 5120 voxels (at most 4096)
+        p.kernel = pf.KERNEL["lds"]
+    elif case == "lds_recorded":
+        g = _grid(1, 2, 1, 9, 10)
+        p.kernel = pf.KERNEL["lds"]
+        p.ckpt_every, p.tape, p.tape_bytes = 1, 512 * 1024, 1 << 30
     elif case == "fused2_2d":
         g = _grid(1, 2, 1, 9, 10)
         p.kernel = pf.KERNEL["fused2"]

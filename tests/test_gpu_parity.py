@@ -215,6 +215,34 @@ def test_fused_equals_two_pass_bitwise(name, storage):
     assert a.energy == b.energy and a.dual == b.dual
 
 
+LDS_CASES = {
+    "potts2d_rects_64x64": lambda: WORKLOADS["potts2d_rects_64x64"](),
+    "potts2d_nl5_B3_nodefield": lambda: synth.random_potts(31, (1, 37, 70), 2, 5, batch=3,
+                                                           s_mode="node_field"),
+    "dag2d_B2_shared": lambda: synth.random_problem(32, (1, 26, 37), 2,
+                                                    synth.random_dag(np.random.default_rng(32), 3, 5),
+                                                    batch=2, s_mode="shared_field"),
+    "ishikawa_levels_48x61": lambda: WORKLOADS["ishikawa_levels_48x61"](),
+    "diff_batch_3x40x52": lambda: WORKLOADS["diff_batch_3x40x52"](),
+    "potts2d_one_row": lambda: synth.random_potts(33, (1, 1, 1000), 2, 3, s_mode="node_scalar"),
+}
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("name", list(LDS_CASES))
+def test_lds_equals_two_pass_bitwise(name, storage):
+    """The LDS-resident 2-D solve keeps each value as the storage type holds
+    it and evaluates the two-pass expressions, so the states agree bit for
+    bit; with gap checks every 7 iterations it runs one launch per chunk."""
+    p = LDS_CASES[name]()
+    for iters, gap_every in ((23, 0), (30, 7)):
+        print(f"[lds] {name} {storage} iters={iters} gap_every={gap_every}", flush=True)
+        a = gpu_solve(p, iters, kernel="two_pass", storage=storage, return_q=True, gap_every=gap_every)
+        b = gpu_solve(p, iters, kernel="lds", storage=storage, return_q=True, gap_every=gap_every)
+        assert torch.equal(a.u, b.u) and torch.equal(a.q, b.q) and torch.equal(a.labels, b.labels)
+        assert a.energy == b.energy and a.dual == b.dual and a.iters_done == b.iters_done
+
+
 FUSED2_CASES = {
     "potts3d_voronoi_36x40x44": lambda: WORKLOADS["potts3d_voronoi_36x40x44"](),
     "potts3d_nl3_B2_nodefield": lambda: synth.random_potts(21, (37, 19, 131), 3, 3, batch=2,
