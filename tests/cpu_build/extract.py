@@ -23,8 +23,10 @@ def main(out):
     # the empty asm that hides a value from the optimiser names a VGPR operand
     k = open(os.path.join(SRC, "pf_kernels.hip")).read().replace(
         '__asm__ volatile("" : "+v"(v));', '__asm__ volatile("" : "+r"(v));')
+    kd = k
     k = k[:k.index("// ----------------------------------------------------------- dispatch ----")]
-    k += "\n}  // namespace\n}  // namespace pf\n"
+    k += "\n}  // namespace\n" + cut(kd, "bool lds_supported(", "hipError_t launch_lds(")
+    k += "\n}  // namespace pf\n"
     f = open(os.path.join(SRC, "pf_fused.hip")).read()
     fk = f[:f.index("template <int ND, typename T, typename F>\nhipError_t fused_bucket")]
     fk += "\n}  // namespace\n" + cut(f, "bool fused_supported(", "hipError_t launch_fused(")

@@ -78,7 +78,7 @@ def gpu_solve(p, iters=None, **kw):
             return pf.solve_hmf(D, S, p.graph, **args)
         return pf.solve_dagmf(D, S, p.graph, **args)
     except pf.PseudoflowError as e:
-        if e.code == pf.PF_EUNSUPPORTED and kw.get("kernel") in ("fused", "fused2"):
+        if e.code == pf.PF_EUNSUPPORTED and kw.get("kernel") in ("fused", "fused2", "lds"):
             pytest.skip(f"no {kw['kernel']} kernel for this problem in this build")
         raise
 

@@ -17,7 +17,7 @@ from parity_util import (check_parity, compare_labels, gpu_solve, oracle_energy_
 pytestmark = pytest.mark.gpu
 torch.set_num_threads(max(1, min(16, torch.get_num_threads())))
 
-KERNELS = ["two_pass", "fused", "fused2"]
+KERNELS = ["two_pass", "fused", "fused2", "lds"]
 
 
 def _kernels_for(p):
@@ -26,6 +26,10 @@ def _kernels_for(p):
         ks.append("fused")
     if p.kind == "potts" and p.ndim == 3 and p.n_leaf <= 8:
         ks.append("fused2")
+    V = p.shape[1] * p.shape[2] * p.shape[3]          # voxels per problem
+    if (p.ndim == 2 and p.n_leaf <= 8 and p.n_node <= 16 and V <= 4096
+            and V * (p.n_leaf + 2 * p.n_node) <= 40960):
+        ks.append("lds")
     return ks
 
 
