@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define PF_ABI_VERSION 2
+#define PF_ABI_VERSION 3      /* 3: PF_KERNEL_LDS */
 #define PF_MAX_LEAVES 16     /* end-labels per problem */
 #define PF_MAX_NODES 32      /* non-source nodes per problem */
 

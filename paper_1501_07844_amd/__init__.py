@@ -40,7 +40,7 @@ EXPORTED = ["pf_workspace_bytes", "solve_potts", "solve_dagmf", "solve_hmf",
             "solve_ishikawa", "pf_last_error", "pf_abi_version", "pf_tape_bytes",
             "pf_backward_workspace_bytes", "pf_potts_backward", "pf_dagmf_backward",
             "pf_auto_kernel"]
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 

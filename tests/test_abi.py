@@ -43,7 +43,7 @@ def test_every_declared_symbol_is_exported():
     lib = pf.library()
     for name in _declared():
         assert hasattr(lib, name), name
-    assert lib.pf_abi_version() == pf.ABI_VERSION == 2
+    assert lib.pf_abi_version() == pf.ABI_VERSION == 3
 
 
 def _grid(B=1, nd=3, Z=8, Y=9, X=10):
