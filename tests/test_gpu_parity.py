@@ -229,7 +229,19 @@ LDS_CASES = {
     "ishikawa_levels_48x61": lambda: WORKLOADS["ishikawa_levels_48x61"](),
     "diff_batch_3x40x52": lambda: WORKLOADS["diff_batch_3x40x52"](),
     "potts2d_one_row": lambda: synth.random_potts(33, (1, 1, 1000), 2, 3, s_mode="node_scalar"),
+    "potts2d_B40_shared": lambda: synth.random_potts(34, (1, 33, 47), 2, 4, batch=40,
+                                                     s_mode="shared_field"),
 }
+
+
+def test_lds_warm_start_continues_exactly():
+    """23 iterations in one LDS-resident solve equal 10 then 13 more from the
+    state the first call left in the workspace."""
+    p = LDS_CASES["potts2d_nl5_B3_nodefield"]()
+    full = gpu_solve(p, 23, kernel="lds", return_q=True)
+    first = gpu_solve(p, 10, kernel="lds", return_q=True)
+    second = gpu_solve(p, 13, kernel="lds", return_q=True, warm_start=True, workspace=first.workspace)
+    assert torch.equal(full.u, second.u) and torch.equal(full.q, second.q)
 
 
 @pytest.mark.parametrize("storage", ["fp32", "bf16", "fp16"])
