@@ -68,10 +68,10 @@ typedef enum {
 
 typedef enum {
     PF_KERNEL_AUTO = 0,      /* the faster variant as measured on MI355X: LDS for
-                                batches of 8 or more 2-D problems whose state fits in
-                                LDS; for 3-D Potts
-                                FUSED2 up to 8 labels (every storage type), beyond
-                                that FUSED with fp32 state; two-pass otherwise */
+                                batches of 8 or more 2-D problems that it supports;
+                                for 3-D Potts FUSED2 up to 8 labels (every storage
+                                type), beyond that FUSED with fp32 state; two-pass
+                                otherwise */
     PF_KERNEL_TWO_PASS = 1,  /* label pass then flow pass, state updated in place */
     PF_KERNEL_FUSED = 2,     /* one pass per iteration, state ping-ponged */
     PF_KERNEL_FUSED2 = 3,    /* one pass per two iterations (3-D Potts, n_leaf <= 8;
