@@ -234,6 +234,20 @@ LDS_CASES = {
 }
 
 
+def test_lds_batch_of_256_images_equals_two_pass():
+    """The benchmark's batch: 256 copies of the 64 x 64 workload, 200
+    iterations, the LDS-resident solve AUTO takes against the two-pass
+    kernels, bit for bit."""
+    p = synth.potts2d_rects()
+    D = torch.from_numpy(np.ascontiguousarray(np.repeat(p.D, 256, axis=0))).cuda()
+    assert pf.auto_kernel((256,) + tuple(p.shape[1:]), 3, 3, 2) == "lds"
+    kw = dict(c=p.c, tau=p.tau, iters=p.iters, ndim=2, s_mode=p.s_mode, return_q=True)
+    a = pf.solve_potts(D, p.S, kernel="two_pass", **kw)
+    b = pf.solve_potts(D, p.S, **kw)
+    assert torch.equal(a.u, b.u) and torch.equal(a.q, b.q) and a.energy == b.energy
+    assert torch.equal(b.u[0], b.u[255])          # identical problems, identical answers
+
+
 def test_lds_warm_start_continues_exactly():
     """23 iterations in one LDS-resident solve equal 10 then 13 more from the
     state the first call left in the workspace."""
