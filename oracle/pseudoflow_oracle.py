@@ -304,41 +304,53 @@ class OracleGraph:
 
 
 def _flow_excess(q, D, graph: OracleGraph, ndim: int) -> Dict[int, torch.Tensor]:
-    """Top-down flow excess d_A for every non-source node (Algorithm 2, first
-    block): d_A = div q_A, leaves add D_L, then in topological order every
-    node pushes w_(A,C) d_A into each child C.  d_S = 0 is never pushed."""
+    """Flow excess d_A of every non-source node, from its definition in the
+    DAGMF section: d_S = 0, and for A != S
+        d_A = div q_A + sum_{P in A.P} w_(P,A) d_P   (+ D_A when A is an end-label).
+    Evaluated as a memoised recursion over the parents (the source term is
+    0), so the value of a node is read straight off the definition."""
     dq = div(q, ndim)                                     # [B][n_node][Z][Y][X]
-    d = {A: dq[:, A - 1] for A in range(1, graph.n_nodes)}
-    for L in graph.leaves:
-        d[L] = d[L] + D[:, graph.leaf_index[L]]
-    for A in graph.order:
+    memo: Dict[int, torch.Tensor] = {}
+
+    def d_of(A: int) -> Optional[torch.Tensor]:
         if A == 0:
-            continue
-        for C in graph.children[A]:
-            d[C] = d[C] + graph.w[(A, C)] * d[A]
-    return d
+            return None                                   # d_S = 0
+        if A not in memo:
+            val = dq[:, A - 1]
+            if A in graph.leaf_index:
+                val = val + D[:, graph.leaf_index[A]]
+            for P in graph.parents[A]:
+                dP = d_of(P)
+                if dP is not None:
+                    val = val + graph.w[(P, A)] * dP
+            memo[A] = val
+        return memo[A]
+
+    return {A: d_of(A) for A in range(1, graph.n_nodes)}
 
 
 def dag_upward(u, graph: OracleGraph) -> Dict[int, torch.Tensor]:
-    """Implicit labels: U_L = u_L on leaves, U_A = sum_{C in A.C} w_(A,C) U_C,
-    accumulated in reverse topological order (the labelling constraint of
-    the DAGMF model)."""
-    U = {A: None for A in range(1, graph.n_nodes)}
-    for L in graph.leaves:
-        U[L] = u[:, graph.leaf_index[L]]
-    for A in reversed(graph.order):
-        if A == 0 or A in graph.leaf_index:
-            continue
-        acc = None
-        for C in graph.children[A]:
-            term = graph.w[(A, C)] * U[C]
-            acc = term if acc is None else acc + term
-        U[A] = acc
-    return U
+    """Implicit labels from the labelling constraint of the DAGMF model:
+    U_L = u_L on end-labels and U_A = sum_{C in A.C} w_(A,C) U_C otherwise,
+    as a memoised recursion over the children."""
+    memo: Dict[int, torch.Tensor] = {}
+
+    def U_of(A: int) -> torch.Tensor:
+        if A not in memo:
+            if A in graph.leaf_index:
+                memo[A] = u[:, graph.leaf_index[A]]
+            else:
+                memo[A] = sum(graph.w[(A, C)] * U_of(C) for C in graph.children[A])
+        return memo[A]
+
+    return {A: U_of(A) for A in range(1, graph.n_nodes)}
 
 
 def dag_iteration(ell, q, D, S, graph: OracleGraph, c: float, tau: float, ndim: int):
-    """One pass of the loop of Algorithm 2 (pseudo-flow DAGMF).
+    """One iteration of the pseudo-flow DAGMF method (Algorithm 2): the flow
+    excess of every end-label, the closed-form entropic label update over the
+    end-labels, then the Chambolle flow update of every non-source node A
+    driven by the implicit label U_A of the normalised end-labels.
 
     ell [B][n_leaf][...], q [B][n_node][nd][...] (node A at index A-1),
     D [B][n_leaf][...], S broadcastable to [B][n_node][Z][Y][X].
@@ -347,20 +359,11 @@ def dag_iteration(ell, q, D, S, graph: OracleGraph, c: float, tau: float, ndim: 
     dl = torch.stack([d[L] for L in graph.leaves], dim=1)
     t = ell - dl / c
     ell = t - torch.logsumexp(t, dim=1, keepdim=True)
-    u = torch.exp(ell)
-    # bottom-up: reuse of the excess buffer as the label accumulator
-    acc = {A: torch.zeros_like(u[:, 0]) for A in range(1, graph.n_nodes)}
-    for L in graph.leaves:
-        acc[L] = u[:, graph.leaf_index[L]]
-    newq = [None] * graph.n_node
-    for A in reversed(graph.order):
-        if A == 0:
-            continue
+    U = dag_upward(torch.exp(ell), graph)
+    newq = []
+    for A in range(1, graph.n_nodes):
         SA = S[:, A - 1] if S.shape[1] > 1 else S[:, 0]
-        newq[A - 1] = project(_zero_last(q[:, A - 1] - c * tau * grad(acc[A], ndim), ndim), SA)
-        for P in graph.parents[A]:
-            if P != 0:
-                acc[P] = acc[P] + graph.w[(P, A)] * acc[A]
+        newq.append(project(_zero_last(q[:, A - 1] - c * tau * grad(U[A], ndim), ndim), SA))
     return ell, torch.stack(newq, dim=1), dl
 
 
@@ -436,33 +439,34 @@ def brute_force_min_energy(D, S, s_mode: str, graph: OracleGraph, ndim: int,
 
 # --------------------------------------------------- Ishikawa model ------
 
+def _ishikawa_excess(q, D, ndim: int) -> torch.Tensor:
+    """Flow excess of the chain labels L_0..L_N (Algorithm 3): d_{L_0} = D_0
+    and d_{L_i} = D_i + sum_{j=1..i} div q_j, i.e. L_i receives the flow of
+    every level at or below it."""
+    dq = div(q, ndim)                                      # [B][N][...]
+    zero = torch.zeros_like(dq[:, :1])
+    return torch.cumsum(torch.cat([zero, dq], dim=1), dim=1) + D
+
+
 def ishikawa_iteration(ell, q, D, S, c: float, tau: float, ndim: int):
-    """One pass of the loop of Algorithm 3 (pseudo-flow Ishikawa), labels
-    L_0..L_N and flows q_1..q_N.
+    """One iteration of the pseudo-flow Ishikawa chain (Algorithm 3), labels
+    L_0..L_N and flows q_1..q_N: the chain's flow excess, the entropic label
+    update, and the Chambolle step of q_i driven by the accumulated label
+    U_i = sum_{j >= i} u_j (the super-object made of L_i and every label
+    above it in the chain).
 
     ell [B][N+1][...], q [B][N][nd][...] (flow of L_i at index i-1),
-    S broadcastable to [B][N][Z][Y][X].  Top-down: d_0 = 0,
-    d_i = d_{i-1} + div q_i, then every label adds D_i.  The label step is
-    the leaf softmax; bottom-up the accumulator for L_i sums u_i..u_N and
-    drives the flow step of q_i (the implicit label of the super-object
-    L_i contains L_i and everything below it in the chain)."""
-    B, n = ell.shape[:2]
-    N = n - 1
-    dq = div(q, ndim)                                      # [B][N][...]
-    d = [torch.zeros_like(ell[:, 0])]
-    for i in range(1, N + 1):
-        d.append(d[i - 1] + dq[:, i - 1])
-    dl = torch.stack(d, dim=1) + D
+    S broadcastable to [B][N][Z][Y][X]."""
+    n = ell.shape[1]
+    dl = _ishikawa_excess(q, D, ndim)
     t = ell - dl / c
     ell = t - torch.logsumexp(t, dim=1, keepdim=True)
     u = torch.exp(ell)
-    acc = [u[:, i] for i in range(N + 1)]
-    for i in range(N - 1, 0, -1):
-        acc[i] = acc[i] + acc[i + 1]
     newq = []
-    for i in range(1, N + 1):
+    for i in range(1, n):
+        Ui = u[:, i:].sum(dim=1)
         Si = S[:, i - 1] if S.shape[1] > 1 else S[:, 0]
-        newq.append(project(_zero_last(q[:, i - 1] - c * tau * grad(acc[i], ndim), ndim), Si))
+        newq.append(project(_zero_last(q[:, i - 1] - c * tau * grad(Ui, ndim), ndim), Si))
     return ell, torch.stack(newq, dim=1), dl
 
 
@@ -479,13 +483,8 @@ def energy_ishikawa(u, D, S, ndim: int) -> torch.Tensor:
 
 
 def dual_ishikawa(q, D, ndim: int) -> torch.Tensor:
-    dq = div(q, ndim)
-    N = dq.shape[1]
-    d = [torch.zeros_like(dq[:, 0])]
-    for i in range(1, N + 1):
-        d.append(d[i - 1] + dq[:, i - 1])
-    dl = torch.stack(d, dim=1) + D
-    return dl.min(dim=1).values.sum(dim=(1, 2, 3))
+    """Pseudo-flow dual per problem: sum_x min_i d_{L_i}."""
+    return _ishikawa_excess(q, D, ndim).min(dim=1).values.sum(dim=(1, 2, 3))
 
 
 def solve_ishikawa(D, S, s_mode: str, c: float, tau: float, iters: int, ndim: int,
