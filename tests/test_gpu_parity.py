@@ -11,8 +11,8 @@ import paper_1501_07844_amd as pf
 from paper_1501_07844_amd import synth
 from oracle import pseudoflow_oracle as O
 
-from parity_util import (check_parity, compare_labels, gpu_solve, oracle_energy_dual,
-                         oracle_solve)
+from parity_util import (check_parity, compare_labels, device_inputs, gpu_solve,
+                         oracle_energy_dual, oracle_solve, supported_kernels)
 
 pytestmark = pytest.mark.gpu
 torch.set_num_threads(max(1, min(16, torch.get_num_threads())))
@@ -21,16 +21,7 @@ KERNELS = ["two_pass", "fused", "fused2", "lds"]
 
 
 def _kernels_for(p):
-    ks = ["two_pass"]
-    if p.kind in ("potts", "hmf", "dagmf"):
-        ks.append("fused")
-    if p.kind == "potts" and p.ndim == 3 and p.n_leaf <= 8:
-        ks.append("fused2")
-    V = p.shape[1] * p.shape[2] * p.shape[3]          # voxels per problem
-    if (p.ndim == 2 and p.n_leaf <= 8 and p.n_node <= 16 and V <= 4096
-            and V * (p.n_leaf + 2 * p.n_node) <= 40960):
-        ks.append("lds")
-    return ks
+    return [k for k in supported_kernels(p) if k != "auto"]
 
 
 def _run_and_check(p, kernel, iters=None, **kw):
@@ -48,6 +39,8 @@ WORKLOADS = {
     "dagmf_blobs_18x30x38": lambda: synth.dagmf_blobs(shape=(18, 30, 38), iters=120),
     "diff_batch_3x40x52": lambda: synth.diff_batch(batch=3, ny=40, nx=52, iters=100),
     "ishikawa_levels_48x61": lambda: synth.ishikawa_levels(shape=(1, 48, 61), iters=150),
+    "ishikawa_levels_20x36x44_n7": lambda: synth.ishikawa_levels(shape=(20, 36, 44), n_levels=7,
+                                                                 iters=120),
 }
 
 
@@ -126,6 +119,8 @@ def test_degenerate_cases():
     p.D[:] = p.D[:, :1]
     r = gpu_solve(p, return_q=True)
     assert float((r.u - 0.25).abs().max()) < 1e-6 and float(r.q.abs().max()) == 0.0
+    # every voxel is an exact four-way tie: the export takes the lowest label
+    assert torch.all(r.u[:, 1:] == r.u[:, :1]) and torch.all(r.labels == 0)
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
@@ -190,7 +185,7 @@ def test_nonfinite_inputs_rejected():
 @pytest.mark.parametrize("storage", ["bf16", "fp16"])
 @pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("name", ["potts3d_voronoi_36x40x44", "hmf_ellipsoids_20x36x44",
-                                  "dagmf_blobs_18x30x38"])
+                                  "dagmf_blobs_18x30x38", "ishikawa_levels_20x36x44_n7"])
 def test_low_precision_storage_energy(name, kernel, storage):
     """Flow and label state stored in 16 bits, float32 arithmetic: the energy
     stays within 1e-3 relative of the float64 reference."""
@@ -231,6 +226,13 @@ LDS_CASES = {
     "potts2d_one_row": lambda: synth.random_potts(33, (1, 1, 1000), 2, 3, s_mode="node_scalar"),
     "potts2d_B40_shared": lambda: synth.random_potts(34, (1, 33, 47), 2, 4, batch=40,
                                                      s_mode="shared_field"),
+    # the label-graph builds of 9..12 and 13..16 flows
+    "tree2d_nn11_B3": lambda: synth.random_problem(35, (1, 20, 30), 2,
+                                                   synth.random_tree(np.random.default_rng(35), 3, 8),
+                                                   batch=3, s_mode="node_field", kind="hmf"),
+    "dag2d_nn15_B2": lambda: synth.random_problem(36, (1, 24, 40), 2,
+                                                  synth.random_dag(np.random.default_rng(36), 7, 8),
+                                                  batch=2, s_mode="node_scalar"),
 }
 
 
@@ -314,12 +316,39 @@ def test_fused2_full_size_equals_fused(storage):
     assert a.energy == b.energy and a.dual == b.dual
 
 
-def test_fused2_rejects_unsupported():
-    for p, why in ((synth.random_potts(1, (1, 9, 11), 2, 4), "2-D"),
-                   (synth.random_potts(2, (3, 5, 7), 3, 12), "12 labels"),
-                   (synth.hmf_ellipsoids(shape=(4, 6, 8), iters=2), "label graph")):
+def _solve_direct(p, iters, **kw):
+    """The C entry point of p's model, without the skip table of gpu_solve."""
+    D, S = device_inputs(p)
+    args = dict(c=p.c, tau=p.tau, iters=iters, ndim=p.ndim, s_mode=p.s_mode, **kw)
+    if p.kind == "potts":
+        return pf.solve_potts(D, S, **args)
+    if p.kind == "ishikawa":
+        return pf.solve_ishikawa(D, S, **args)
+    if p.kind == "hmf":
+        return pf.solve_hmf(D, S, p.graph, **args)
+    return pf.solve_dagmf(D, S, p.graph, **args)
+
+
+def test_unsupported_kernels_are_rejected():
+    """Every documented PF_EUNSUPPORTED case returns that code through the
+    C ABI (and leaves nothing half-done): two iterations per pass outside 3-D
+    Potts up to 8 labels, the fused pass for the Ishikawa chain or beyond 16
+    flows, the LDS-resident solve for 3-D or oversized 2-D problems."""
+    deep = synth.random_problem(201, (3, 5, 6), 3, synth.random_dag(np.random.default_rng(7), 15, 16,
+                                                                    max_parents=2))
+    cases = ((synth.random_potts(1, (1, 9, 11), 2, 4), "fused2", "2-D"),
+             (synth.random_potts(2, (3, 5, 7), 3, 12), "fused2", "12 labels"),
+             (synth.hmf_ellipsoids(shape=(4, 6, 8), iters=2), "fused2", "label graph"),
+             (synth.ishikawa_levels(shape=(1, 9, 10), iters=2), "fused", "Ishikawa chain"),
+             (synth.ishikawa_levels(shape=(1, 9, 10), iters=2), "fused2", "Ishikawa chain"),
+             (deep, "fused", "30 flows"),
+             (synth.random_potts(3, (3, 5, 7), 3, 3), "lds", "3-D"),
+             (synth.random_potts(4, (1, 70, 70), 2, 3), "lds", "4900 voxels"),
+             (synth.random_potts(5, (1, 30, 30), 2, 12), "lds", "12 labels"))
+    for p, kernel, why in cases:
+        assert kernel not in supported_kernels(p), why
         with pytest.raises(pf.PseudoflowError) as ei:
-            gpu_solve(p, 2, kernel="fused2")
+            _solve_direct(p, 2, kernel=kernel)
         assert ei.value.code == pf.PF_EUNSUPPORTED, why
 
 

@@ -150,6 +150,8 @@ def test_equal_data_terms_are_stationary():
     res = O.solve_potts(p.D, p.S, p.s_mode, 2.0, 0.1, 15, 3, history=False)
     assert torch.allclose(res["u"], torch.full_like(res["u"], 0.25), atol=1e-15)
     assert float(res["q"].abs().max()) == 0.0
+    # exact ties everywhere: the argmax reading takes the lowest label
+    assert torch.all(res["u"][:, 1:] == res["u"][:, :1]) and torch.all(res["labels"] == 0)
 
 
 # ------------------------------------------------- feasibility / duality -
