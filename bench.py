@@ -1,25 +1,30 @@
 """Throughput of the pseudo-flow solvers on one MI355X.
 
-Headline workload: Potts 3-D, 256^3 voxels, 8 labels, float32 state and
-arithmetic, 500 iterations (seeded 64-site Voronoi phantom, noise 0.15,
-Gaussian-NLL data terms, S(x) = 0.3 exp(-|grad I|^2 / 0.01)).  One step is one
-complete solve: initialisation, 500 iterations, the float64 energy/dual/gap
-evaluation and the argmax export.  Inputs are resident in HBM before timing
-starts.
+Headline workload: DAGMF on a 3-D grid of 256 x 512 x 512 voxels, a label DAG
+of 4 shared parents and 12 leaves (16 flows, two random parents per leaf),
+bf16 flow and label storage with float32 arithmetic and float64 energy/gap
+reductions, 300 iterations (seeded random-blob phantom: 64 balls of radius
+U[16, 64] and class U{1..11} on background 0, noise 0.1, Gaussian-NLL data
+terms, S_A ~ U[0.1, 1]).  One step is one complete solve: initialisation, 300
+iterations, the float64 energy/dual/gap evaluation and the argmax export.
+Inputs are resident in HBM before timing starts.
 
 Prints one JSON line: voxel-label iterations per second (voxel-label = voxels
-x non-source label nodes) of the headline solve; the roofline of its kernel
-(one launch covers two iterations with k_fused2), timed with HIP events inside
-the timed region; the per-iteration kernel rates of every workload (Potts 3-D, HMF, DAGMF and an
-Ishikawa chain scaled to 128 x 256 x 256 with 8 ordered labels; float32, bf16
-and fp16 state), whole-solve rates of the two small 2-D cases (Potts and
-Ishikawa) and of a batch of 256 of the Potts case (LDS-resident solve against
-the two-pass kernels); a plain device copy as the achievable bandwidth;
-the cost of the differentiable solve; and the float64 reference
-implementation timed on a bounded sample on the host.
+x non-source label nodes) of the headline solve; the roofline of its kernel,
+timed with HIP events inside the timed region; whole solves of the 256^3
+Potts workload (8 labels, float32, 500 iterations) with the roofline of its
+two-iteration kernel; the per-iteration kernel rates of every workload
+(Potts 3-D, HMF, DAGMF and an Ishikawa chain scaled to 128 x 256 x 256 with 8
+ordered labels; float32, bf16 and fp16 state), whole-solve rates of the two
+small 2-D cases (Potts and Ishikawa) and of a batch of 256 of the Potts case;
+the primal-dual gap after every iteration of the Potts and DAGMF solves; a
+plain device copy as the achievable bandwidth; the cost of the
+differentiable solve; and the float64 reference implementation timed on a
+bounded sample on the host.
 
 ``--counters`` runs only a short program for rocprofv3 counter passes: a
-device copy of known size, then a few launches of the headline kernel.
+device copy of known size, then a few launches of the chosen workload's
+kernel.
 """
 from __future__ import annotations
 
@@ -35,23 +40,36 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-ITERS = 500
 COPY_BYTES = 1 << 30          # the copy kernel moves 1 GiB in and 1 GiB out
+HEADLINE_STORAGE = "bf16"
+POTTS_ITERS = 500
+
+# the sources each timed kernel is built from (its traffic record is valid
+# only while they hash to the recorded value)
+KERNEL_SOURCES = {
+    "k_flow_label": ("pf_flowlabel.hip", "pf_device.h", "pf_internal.h"),
+    "k_fused2": ("pf_fused.hip", "pf_device.h", "pf_internal.h"),
+    "k_fused": ("pf_fused.hip", "pf_device.h", "pf_internal.h"),
+    "k_label+k_flow": ("pf_kernels.hip", "pf_device.h", "pf_internal.h"),
+}
+TRAFFIC_FILES = {"dagmf": "traffic_dagmf_256x512x512_bf16.json",
+                 "potts3d": "traffic_potts3d_256.json"}
 
 
-def _kernel_source_hash() -> str:
-    """Hash of the sources the headline kernel is built from."""
+def _kernel_source_hash(kernel: str) -> str:
+    """Hash of the sources `kernel` is built from."""
     h = hashlib.sha256()
-    for f in ("pf_fused.hip", "pf_device.h", "pf_internal.h"):
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_1501_07844_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel: str, source_hash: str):
+def _traffic(which: str, kernel: str, source_hash: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, only while the kernel sources are the ones it was taken on."""
-    path = os.path.join(ROOT, "profiles", "traffic_potts3d_256.json")
+    summary of workload `which`, only while the kernel sources are the ones
+    it was taken on."""
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILES[which])
     try:
         with open(path) as fh:
             rec = json.load(fh)
@@ -88,14 +106,23 @@ def _solver(pf, p):
     return lambda D, S, **kw: pf.solve_dagmf(D, S, p.graph, **kw)
 
 
-KERNEL_NAMES = {"fused2": "k_fused2", "fused": "k_fused", "two_pass": "k_label+k_flow"}
+KERNEL_NAMES = {"fused2": "k_fused2", "fused": "k_fused", "two_pass": "k_label+k_flow",
+                "lds": "k_lds2d"}
+
+
+def _kernel_name(p, choice: str) -> str:
+    """The kernel a choice launches per iteration: the fused kind on a 3-D
+    label graph is the flow-then-label pass."""
+    if choice == "fused" and p.kind != "potts" and p.ndim == 3:
+        return "k_flow_label"
+    return KERNEL_NAMES[choice]
 
 
 def _kernel_choice(pf, p, storage: str, kernel: str) -> str:
+    """The kernel the library runs (AUTO resolved by the library's own rule;
+    the Ishikawa chain follows the label-graph rule)."""
     if kernel != "auto":
         return kernel
-    if p.kind == "ishikawa":
-        return "two_pass"
     return pf.auto_kernel(p.shape, p.n_leaf, p.n_node, p.ndim, storage,
                           identity=p.kind == "potts")
 
@@ -125,7 +152,7 @@ def kernel_leg(p, storage: str, iters: int, dev, kernel: str = "auto") -> dict:
     launch = ba * V / (per_launch * ms * 1e-3) / 1e9
     out = {"workload": f"{p.name} {'x'.join(map(str, p.shape[1:]))}"
                        + (f" x{p.shape[0]}" if p.shape[0] > 1 else ""),
-           "storage": storage, "kernel": KERNEL_NAMES[choice],
+           "storage": storage, "kernel": _kernel_name(p, choice),
            "ms_per_iter": round(ms, 4), "iterations_timed": r.kernel_timed,
            "iterations_per_launch": per_launch,
            "voxel_label_its_per_s": V * p.n_node / (ms * 1e-3),
@@ -309,12 +336,13 @@ def ishikawa2d_leg(dev, reps: int = 5) -> dict:
             "energy": r.energy, "gap": r.gap}
 
 
-def counters_program(which: str = "potts3d", kernel: str = "auto") -> int:
-    """Short program for rocprofv3 counter passes.  "potts3d": one copy of
-    COPY_BYTES (the calibration kernel), then 6 iterations of the headline
-    solve (3 launches of k_fused2 with the AUTO choice; `kernel` overrides
-    it).  "graphs": 3 two-pass iterations of DAGMF at 128x256x256 and of
-    Potts-3D at 128^3 (fp32)."""
+def counters_program(which: str = "dagmf", kernel: str = "auto") -> int:
+    """Short program for rocprofv3 counter passes.  "dagmf": one copy of
+    COPY_BYTES (the calibration kernel), then 3 iterations of the headline
+    solve (3 launches of its kernel).  "potts3d": the copy, then 6 iterations
+    of the 256^3 Potts solve (3 launches of k_fused2 with the AUTO choice).
+    "graphs": 3 two-pass iterations of DAGMF at 128x256x256 and of Potts-3D
+    at 128^3 (fp32).  `kernel` overrides the AUTO choice."""
     import torch
 
     import paper_1501_07844_amd as pf
@@ -324,7 +352,7 @@ def counters_program(which: str = "potts3d", kernel: str = "auto") -> int:
         p = synth.dagmf_blobs(shape=(128, 256, 256))
         D = torch.from_numpy(p.D).to(dev)
         pf.solve_dagmf(D, p.S, p.graph, c=p.c, tau=p.tau, iters=3, ndim=3, s_mode=p.s_mode,
-                       final_energy=False, return_u=False, return_labels=False)
+                       kernel="two_pass", final_energy=False, return_u=False, return_labels=False)
         q = synth.potts3d_voronoi(n=128)
         D2, S2 = _inputs(q, dev)
         pf.solve_potts(D2, S2, c=q.c, tau=q.tau, iters=3, ndim=3, s_mode=q.s_mode,
@@ -337,14 +365,112 @@ def counters_program(which: str = "potts3d", kernel: str = "auto") -> int:
     b.copy_(a)
     torch.cuda.synchronize()
     del a, b
-    p = synth.potts3d_voronoi(n=256, iters=6)
-    D, S = _inputs(p, dev)
-    r = pf.solve_potts(D, S, c=p.c, tau=p.tau, iters=6, ndim=3, s_mode=p.s_mode, kernel=kernel,
-                       final_energy=False, return_u=False, return_labels=False)
+    if which == "potts3d":
+        p = synth.potts3d_voronoi(n=256, iters=6)
+        D, S = _inputs(p, dev)
+        r = pf.solve_potts(D, S, c=p.c, tau=p.tau, iters=6, ndim=3, s_mode=p.s_mode,
+                           kernel=kernel, final_energy=False, return_u=False, return_labels=False)
+        choice = _kernel_choice(pf, p, "fp32", kernel)
+    else:
+        p = synth.dagmf_blobs(iters=3)
+        D = torch.from_numpy(p.D).to(dev)
+        r = pf.solve_dagmf(D, p.S, p.graph, c=p.c, tau=p.tau, iters=3, ndim=3, s_mode=p.s_mode,
+                           storage=HEADLINE_STORAGE, kernel=kernel, final_energy=False,
+                           return_u=False, return_labels=False)
+        choice = _kernel_choice(pf, p, HEADLINE_STORAGE, kernel)
     torch.cuda.synchronize()
-    print(json.dumps({"counters_program": "done", "iters": r.iters_done,
-                      "source_hash": _kernel_source_hash()}), flush=True)
+    name = _kernel_name(p, choice)
+    print(json.dumps({"counters_program": which, "iters": r.iters_done, "kernel": name,
+                      "source_hash": _kernel_source_hash(name) if name in KERNEL_SOURCES else None}),
+          flush=True)
     return 0
+
+
+def timed_solves(pf, solve, D, S, kw, steps: int, warmup: int, stride: int):
+    """`warmup` untimed solves, then `steps` solves timed as a whole
+    (synchronised on both sides) with the launch starting every `stride`-th
+    iteration also bracketed by HIP events on the library's stream."""
+    import torch
+    ws = res = None
+    for _ in range(warmup):
+        res = solve(D, S, workspace=ws, **kw)
+        ws = res.workspace
+    torch.cuda.synchronize()
+    kms, kn = 0.0, 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = solve(D, S, workspace=ws, timing_stride=stride, **kw)
+        ws = res.workspace
+        kms += res.kernel_ms
+        kn += res.kernel_timed
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, kms, kn, res
+
+
+def roofline_of(which: str, kernel_name: str, per_launch: int, bytes_per_launch: int,
+                kms: float, kn: int) -> dict:
+    """Roofline object of a timed kernel: algorithmic bytes per launch (the
+    state read and written once, data terms and capacity fields read once)
+    over the mean launch duration from HIP events, against 8 TB/s."""
+    avg_ms = kms / max(kn, 1) * per_launch
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    src_hash = _kernel_source_hash(kernel_name) if kernel_name in KERNEL_SOURCES else None
+    traffic = _traffic(which, kernel_name, src_hash) if src_hash else None
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": kernel_name, "kernel_avg_ms": round(avg_ms, 4),
+            "iterations_per_launch": per_launch, "kernel_launches_timed": kn // per_launch,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "iteration_equivalent_GBs": round(achieved * per_launch, 1),
+            "iteration_equivalent_frac": round(achieved * per_launch / HBM_PEAK_GBS, 4),
+            "source_hash": src_hash}
+
+
+def potts3d_leg(dev, n: int, steps: int = 2) -> dict:
+    """Whole solves of the 256^3 Potts workload (8 labels, float32 state, 500
+    iterations; two iterations per launch under AUTO), one warm-up, and the
+    roofline of its kernel from HIP events around every 25th iteration."""
+    import paper_1501_07844_amd as pf
+    from paper_1501_07844_amd import synth
+    p = synth.potts3d_voronoi(n=n, iters=POTTS_ITERS)
+    D, S = _inputs(p, dev)
+    kw = dict(c=p.c, tau=p.tau, iters=POTTS_ITERS, ndim=3, s_mode=p.s_mode, kernel="auto",
+              final_energy=True, return_u=False, return_labels=True)
+    elapsed, kms, kn, res = timed_solves(pf, pf.solve_potts, D, S, kw, steps, 1, 25)
+    choice = _kernel_choice(pf, p, "fp32", "auto")
+    per_launch = 2 if choice == "fused2" else 1
+    V = p.voxels
+    out = {"workload": f"potts3d_voronoi {n}x{n}x{n}, 8 labels, {POTTS_ITERS} iterations, "
+                       f"c={p.c}, tau={p.tau}, fp32 state",
+           "ms_per_solve": round(1e3 * elapsed / steps, 2),
+           "voxel_label_its_per_s": V * p.n_node * POTTS_ITERS * steps / elapsed,
+           "energy": res.energy, "gap": res.gap,
+           "roofline": roofline_of("potts3d", _kernel_name(p, choice), per_launch,
+                                   bytes_alg(p, "fp32") * V, kms, kn)}
+    print(f"[bench] potts3d: {out['ms_per_solve']} ms/solve", file=sys.stderr, flush=True)
+    return out
+
+
+def gap_leg(dev, p, storage: str) -> dict:
+    """The primal-dual gap after every iteration of a whole solve (not
+    timed): how often it increases and by how much relative to the energy."""
+    import torch
+
+    import paper_1501_07844_amd as pf
+    D, S = _inputs(p, dev)
+    solve = _solver(pf, p)
+    r = solve(D, S, c=p.c, tau=p.tau, iters=p.iters, ndim=p.ndim, s_mode=p.s_mode,
+              storage=storage, gap_every=1, gap_history_cap=p.iters, final_energy=False,
+              return_u=False, return_labels=False)
+    g = r.gap_history
+    inc = [(k + 1, (b - a) / abs(r.energy)) for k, (a, b) in enumerate(zip(g, g[1:])) if b > a]
+    del D, S, r
+    torch.cuda.empty_cache()
+    return {"workload": f"{p.name} {'x'.join(map(str, p.shape[1:]))}", "storage": storage,
+            "iterations": len(g), "gap_first": g[0] if g else None, "gap_last": g[-1] if g else None,
+            "increases": len(inc), "first_increase_after": inc[0][0] if inc else None,
+            "max_increase_rel_energy": max((d for _, d in inc), default=0.0),
+            "min_gap_rel_energy": min(g) / abs(g[-1] if g else 1.0) if g else None}
 
 
 def main() -> int:
@@ -352,13 +478,14 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")
-    ap.add_argument("--kernel", default="auto", choices=["auto", "two_pass", "fused", "fused2"])
+    ap.add_argument("--n", type=int, default=256, help="Potts grid edge (default 256)")
+    ap.add_argument("--kernel", default="auto",
+                    choices=["auto", "two_pass", "fused", "fused2", "lds"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-workloads", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--counters", nargs="?", const="potts3d", default=None,
-                    choices=["potts3d", "graphs"])
+    ap.add_argument("--counters", nargs="?", const="dagmf", default=None,
+                    choices=["dagmf", "potts3d", "graphs"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
@@ -373,67 +500,41 @@ def main() -> int:
     from paper_1501_07844_amd import synth
 
     t0 = time.time()
-    p = synth.potts3d_voronoi(n=args.n, iters=ITERS)
-    print(f"[bench] inputs {p.shape} x {p.n_leaf} labels generated in {time.time() - t0:.1f}s",
-          file=sys.stderr, flush=True)
+    p = synth.dagmf_blobs()
+    print(f"[bench] inputs {p.shape} x {p.n_leaf} leaves / {p.n_node} flows generated in "
+          f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
-    D = torch.from_numpy(p.D).to(dev)
-    S = torch.from_numpy(p.S).to(dev)
+    D, S = _inputs(p, dev)
     B, Z, Y, X = p.shape
     V = B * Z * Y * X
-    n_node = p.n_node
-    kw = dict(c=p.c, tau=p.tau, iters=ITERS, ndim=3, s_mode="shared_field",
+    iters = p.iters
+    kw = dict(c=p.c, tau=p.tau, iters=iters, ndim=3, s_mode=p.s_mode, storage=HEADLINE_STORAGE,
               kernel=args.kernel, final_energy=True, return_u=False, return_labels=True)
-
-    ws = None
-    res = None
-    for _ in range(args.warmup):
-        res = pf.solve_potts(D, S, workspace=ws, **kw)
-        ws = res.workspace
-    torch.cuda.synchronize()
-    kms, kn = 0.0, 0
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        res = pf.solve_potts(D, S, workspace=ws, timing_stride=25, **kw)
-        ws = res.workspace
-        kms += res.kernel_ms
-        kn += res.kernel_timed
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
+    solve = _solver(pf, p)
+    elapsed, kms, kn, res = timed_solves(pf, solve, D, S, kw, args.steps, args.warmup, 10)
     ms_per_step = 1e3 * elapsed / args.steps
-    value = V * n_node * ITERS * args.steps / elapsed
-    print(f"[bench] fp32: {ms_per_step:.1f} ms/step, energy {res.energy:.6e}, gap {res.gap:.3e}",
-          file=sys.stderr, flush=True)
-
-    choice = _kernel_choice(pf, p, "fp32", args.kernel)
-    kernel_name = KERNEL_NAMES[choice]
-    per_launch = 2 if choice == "fused2" else 1                    # iterations per launch
-    # a launch reads and writes the state once whether it covers one or two
-    # iterations: algorithmic bytes per launch = bytes of one iteration
-    ba = bytes_alg(p, "fp32") * V
-    avg_ms = kms / max(kn, 1) * per_launch                         # per launch
-    achieved = ba / (avg_ms * 1e-3) / 1e9
-    src_hash = _kernel_source_hash()
-    traffic = _traffic(kernel_name, src_hash)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": kernel_name, "kernel_avg_ms": round(avg_ms, 4),
-                "iterations_per_launch": per_launch,
-                "kernel_launches_timed": kn // per_launch, "algorithmic_bytes_per_launch": ba,
-                "iteration_equivalent_GBs": round(achieved * per_launch, 1),
-                "source_hash": src_hash}
-    del D, S, ws, res
+    value = V * p.n_node * iters * args.steps / elapsed
+    print(f"[bench] dagmf {HEADLINE_STORAGE}: {ms_per_step:.1f} ms/step, energy {res.energy:.6e}, "
+          f"gap {res.gap:.3e}", file=sys.stderr, flush=True)
+    choice = _kernel_choice(pf, p, HEADLINE_STORAGE, args.kernel)
+    roofline = roofline_of("dagmf", _kernel_name(p, choice), 1, bytes_alg(p, HEADLINE_STORAGE) * V,
+                           kms, kn)
+    headline_energy, headline_gap = res.energy, res.gap
+    del D, S, res
+    torch.cuda.empty_cache()
 
     out = {
         "metric": "voxel-label iterations/s + % HBM peak; FP32 vs BF16-storage at \u22641e-3 rel energy",
         "value": value, "unit": "voxel-label-iterations/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (seeded Voronoi phantom)",
-        "config": {"workload": f"potts3d_voronoi {Z}x{Y}x{X}, 8 labels, {ITERS} iterations, "
-                               f"c={p.c}, tau={p.tau}, fp32 state",
-                   "voxels": V, "labels": p.n_leaf, "iterations": ITERS,
-                   "kernel": args.kernel},
+        "data": "synthetic (seeded random-blob phantom)",
+        "config": {"workload": f"dagmf_blobs {Z}x{Y}x{X}, 4 parents x 12 leaves (16 flows), "
+                               f"{iters} iterations, c={p.c}, tau={p.tau:.6g}, "
+                               f"{HEADLINE_STORAGE} state, fp32 arithmetic, fp64 gap",
+                   "voxels": V, "leaves": p.n_leaf, "label_nodes": p.n_node,
+                   "iterations": iters, "storage": HEADLINE_STORAGE, "kernel": args.kernel,
+                   "energy": headline_energy, "rel_gap": headline_gap / abs(headline_energy)},
         "roofline": roofline,
     }
     out["copy_peak"] = copy_leg(dev)
@@ -442,13 +543,17 @@ def main() -> int:
     torch.cuda.empty_cache()
 
     if not args.no_workloads:
+        out["potts3d"] = potts3d_leg(dev, args.n)
+        out["potts3d"]["roofline"]["frac_of_copy_peak"] = round(
+            out["potts3d"]["roofline"]["achieved"] / out["copy_peak"]["GBs"], 4)
+        torch.cuda.empty_cache()
         legs = []
-        for make, iters in ((lambda: synth.potts3d_voronoi(n=args.n), 20),
-                            (synth.hmf_ellipsoids, 20), (synth.dagmf_blobs, 10),
-                            (lambda: synth.ishikawa_levels(shape=(128, 256, 256), n_levels=7), 20)):
+        for make, kiters in ((lambda: synth.potts3d_voronoi(n=args.n), 20),
+                             (synth.hmf_ellipsoids, 20), (lambda: p, 10),
+                             (lambda: synth.ishikawa_levels(shape=(128, 256, 256), n_levels=7), 20)):
             q = make()
             for storage in ("fp32", "bf16", "fp16"):
-                leg = kernel_leg(q, storage, iters, dev)
+                leg = kernel_leg(q, storage, kiters, dev)
                 print(f"[bench] {leg['workload']} {storage}: {leg['ms_per_iter']} ms/iter, "
                       f"{leg['alg_GBs']} GB/s alg", file=sys.stderr, flush=True)
                 legs.append(leg)
@@ -470,6 +575,8 @@ def main() -> int:
                                 "rel_energy_at_budget": g["rel_energy_full_vs_fp32"],
                                 "iterations": g["iterations_full"]}
                                for g in legs if g["storage"] == "bf16"]
+        out["gap_behaviour"] = [gap_leg(dev, synth.potts3d_voronoi(n=args.n, iters=POTTS_ITERS), "fp32"),
+                                gap_leg(dev, p, HEADLINE_STORAGE)]
         out["potts2d"] = potts2d_leg(dev)
         out["potts2d_batch"] = potts2d_batch_leg(dev)
         torch.cuda.empty_cache()
@@ -486,34 +593,28 @@ def main() -> int:
     return 0
 
 
-def cpu_baseline(p) -> dict:
+def cpu_baseline(p, nz: int = 16, iters: int = 2) -> dict:
     """The float64 reference implementation, as it stands, on a bounded
-    sample: the first 64 z-planes of the same volume, 12 iterations (about
-    10 s on 16 host threads)."""
+    sample of the headline workload: its first `nz` z-planes (all of y and
+    x, the same graph, data terms and capacities), `iters` iterations (about
+    10-20 s on 16 host threads)."""
     import torch
     from oracle import pseudoflow_oracle as O
 
-    nz = min(64, p.shape[1])
+    nz = min(nz, p.shape[1])
     D = p.D[:, :, :nz]
-    S = p.S[:, :nz]
-    iters = 12
+    g = O.OracleGraph(p.graph.n_nodes, p.graph.parent, p.graph.child, p.graph.weight)
     n_threads = max(1, min(16, os.cpu_count() or 1))
     torch.set_num_threads(n_threads)
     t0 = time.perf_counter()
-    O.solve_potts(D, S, p.s_mode, p.c, p.tau, iters, 3, history=False)
+    O.solve_dagmf(D, p.S, p.s_mode, g, p.c, p.tau, iters, 3, history=False)
     dt = time.perf_counter() - t0
     V = D.shape[0] * nz * D.shape[3] * D.shape[4]
-    # the same sample for one iteration on one thread
-    torch.set_num_threads(1)
-    t1 = time.perf_counter()
-    O.solve_potts(D, S, p.s_mode, p.c, p.tau, 1, 3, history=False)
-    dt1 = time.perf_counter() - t1
-    torch.set_num_threads(n_threads)
     return {"value": V * p.n_node * iters / dt, "unit": "voxel-label-iterations/s",
             "cores": n_threads, "kind": "oracle",
-            "sample": f"first {nz} z-planes ({nz}x{D.shape[3]}x{D.shape[4]}), {iters} iterations, "
-                      f"float64, {dt:.1f}s",
-            "single_thread_value": V * p.n_node / dt1}
+            "sample": f"first {nz} z-planes of the headline volume ({nz}x{D.shape[3]}x{D.shape[4]}, "
+                      f"{p.n_leaf} leaves / {p.n_node} flows), {iters} iterations, float64, "
+                      f"{dt:.1f}s"}
 
 
 if __name__ == "__main__":

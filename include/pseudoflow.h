@@ -70,10 +70,18 @@ typedef enum {
     PF_KERNEL_AUTO = 0,      /* the faster variant as measured on MI355X: LDS for
                                 batches of 8 or more 2-D problems that it supports;
                                 for 3-D Potts FUSED2 up to 8 labels (every storage
-                                type), beyond that FUSED with fp32 state; two-pass
-                                otherwise */
+                                type), beyond that FUSED with fp32 state; FUSED for
+                                3-D label graphs (DAGMF, HMF, Ishikawa chain) of 9 to
+                                16 flows and at most 16 leaves with fp32 state;
+                                two-pass otherwise */
     PF_KERNEL_TWO_PASS = 1,  /* label pass then flow pass, state updated in place */
-    PF_KERNEL_FUSED = 2,     /* one pass per iteration, state ping-ponged */
+    PF_KERNEL_FUSED = 2,     /* one pass per iteration, state ping-ponged (at most 16
+                                leaves and 16 flows; 3-D label graphs run the flow
+                                step of one iteration and the label step of the next
+                                in one pass, entered and left with a label pass and a
+                                flow pass around every gap check; not for the
+                                Ishikawa chain in 2-D); the same result as
+                                PF_KERNEL_TWO_PASS bit for bit */
     PF_KERNEL_FUSED2 = 3,    /* one pass per two iterations (3-D Potts, n_leaf <= 8;
                                 PF_EUNSUPPORTED otherwise), state ping-ponged; an
                                 iteration that ends on a gap check, or the last of an
@@ -151,10 +159,10 @@ size_t pf_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t n_node,
                           const pf_params *params);
 
 /* The kernel PF_KERNEL_AUTO runs for an unrecorded solve of this problem:
- * identity != 0 for the Potts model, 0 for a label graph (the Ishikawa chain
- * always runs PF_KERNEL_TWO_PASS); storage is a pf_storage.  Host only, no
- * device work.  Returns PF_KERNEL_TWO_PASS, PF_KERNEL_FUSED, PF_KERNEL_FUSED2
- * or PF_KERNEL_LDS, or -1 for arguments no solver accepts. */
+ * identity != 0 for the Potts model, 0 for a label graph (DAGMF, HMF, and the
+ * Ishikawa chain, whose AUTO follows the same rule); storage is a pf_storage.
+ * Host only, no device work.  Returns PF_KERNEL_TWO_PASS, PF_KERNEL_FUSED,
+ * PF_KERNEL_FUSED2 or PF_KERNEL_LDS, or -1 for arguments no solver accepts. */
 int32_t pf_auto_kernel(const pf_grid *grid, int32_t n_leaf, int32_t n_node, int32_t identity,
                        int32_t storage);
 
@@ -188,8 +196,10 @@ int solve_hmf(const pf_grid *grid, const pf_graph *graph, const float *D, const 
 /* Pseudo-flow Ishikawa chain (Algorithm 3): labels L_0..L_N (n_labels = N+1),
  * flows q_1..q_N; flow excess d_i = D_i + sum_{j<=i} div q_j and the flow of
  * L_i driven by U_i = sum_{j>=i} u_j.  D: device float[B][N+1][Z][Y][X];
- * S per s_mode with n_node = N.  Supports PF_KERNEL_TWO_PASS, PF_KERNEL_LDS
- * and AUTO (LDS for batches of 8 or more problems that fit, else two-pass). */
+ * S per s_mode with n_node = N.  Supports PF_KERNEL_TWO_PASS, PF_KERNEL_LDS,
+ * PF_KERNEL_FUSED on 3-D grids, and AUTO (the rule of pf_auto_kernel with
+ * identity = 0: LDS for batches of 8 or more 2-D problems that fit, FUSED on
+ * 3-D grids, else two-pass). */
 int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
                    int32_t s_mode, const pf_params *params, pf_result *result, void *stream);
 

@@ -284,11 +284,16 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
                               fused2_preferred(p.g.ndim, p.nl, p.nn, p.ident, P->storage)));
     const bool want_fused = want_fused2 || (!P->tape && !want_lds && (P->kernel == PF_KERNEL_FUSED ||
                             (P->kernel == PF_KERNEL_AUTO &&
-                             fused_preferred(p.g.ndim, p.nl, p.nn, p.ident, P->storage))));
+                             any_fused_preferred(p.g.ndim, p.nl, p.nn, p.ident, P->storage))));
     if (P->kernel == PF_KERNEL_FUSED && !fused_supported(p.g.ndim, p.nl, p.nn, p.ident))
         return fail(PF_EUNSUPPORTED, "fused kernel unavailable for this problem");
     if (want_fused2 && !fused2_supported(p.g.ndim, p.nl, p.nn, p.ident))
         return fail(PF_EUNSUPPORTED, "two-iteration kernel unavailable for this problem");
+    // 3-D label graphs: the fused pass is the flow step of one iteration and
+    // the label step of the next (entered with a label pass, left with a flow
+    // pass); the label-then-flow fused kernel serves Potts and 2-D graphs
+    const bool want_fl = want_fused && !want_fused2 &&
+                         flow_label_supported(p.g.ndim, p.nl, p.nn, p.ident);
     const Layout lay = make_layout(p.g, p.nl, p.nn, P->storage, want_fused);
     if (P->workspace_bytes < lay.total)
         return fail(PF_ENOMEM, "workspace of %zu bytes < %zu needed", P->workspace_bytes, lay.total);
@@ -385,11 +390,13 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
         // two iterations in one pass unless a gap check falls after the first
         const bool pair = want_fused2 && it + 1 < P->iters &&
                           !(P->gap_every > 0 && (it + 1) % P->gap_every == 0);
-        // the LDS kernel runs every iteration up to the next gap check
-        const int step = want_lds ? (P->gap_every > 0 ? std::min(P->iters - it,
-                                                                  P->gap_every - it % P->gap_every)
-                                                      : P->iters - it)
-                                  : pair ? 2 : 1;
+        // the LDS kernel and the flow-then-label passes run every iteration up
+        // to the next gap check
+        const int step = (want_lds || want_fl)
+                             ? (P->gap_every > 0 ? std::min(P->iters - it,
+                                                            P->gap_every - it % P->gap_every)
+                                                 : P->iters - it)
+                             : pair ? 2 : 1;
         if (P->tape && it % P->ckpt_every == 0) {
             char *slot = static_cast<char *>(P->tape) + (size_t)(it / P->ckpt_every) * tg.slot_bytes;
             if ((e = launch_copy_f(static_cast<const float *>(ell[0]), reinterpret_cast<float *>(slot),
@@ -398,7 +405,7 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
                                    reinterpret_cast<float *>(slot + tg.ell_bytes), n_q, stream)) != hipSuccess)
                 return hip_fail(e, "checkpoint");
         }
-        const bool timed = P->timing_stride > 0 && (want_lds || it % P->timing_stride == 0);
+        const bool timed = !want_fl && P->timing_stride > 0 && (want_lds || it % P->timing_stride == 0);
         if (timed) {
             hipEvent_t e0, e1;
             if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -410,6 +417,41 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
         if (want_lds) {
             if ((e = launch_lds(a, ident, P->storage, step, stream)) != hipSuccess)
                 return hip_fail(e, "LDS-resident iterations");
+        } else if (want_fl) {
+            // label step of iteration it + 1 in place, `step - 1` passes each
+            // taking the flows and the labels one iteration further (ping-pong),
+            // then the flow step of iteration it + step in place; with timing,
+            // the passes starting every timing_stride-th iteration are timed
+            a.ell_in = a.ell_out = ell[cur];
+            a.q_in = a.q_out = q[cur];
+            if ((e = launch_label(a, ident, nd, P->storage, stream)) != hipSuccess)
+                return hip_fail(e, "label pass");
+            for (int j = 1; j < step; ++j) {
+                a.ell_in = ell[cur];
+                a.q_in = q[cur];
+                a.ell_out = ell[1 - cur];
+                a.q_out = q[1 - cur];
+                const bool tj = P->timing_stride > 0 && (it + j) % P->timing_stride == 0;
+                if (tj) {
+                    hipEvent_t e0, e1;
+                    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+                        return fail(PF_EHIP, "hipEventCreate failed");
+                    timer.ev.push_back(e0);
+                    timer.ev.push_back(e1);
+                    hipEventRecord(e0, stream);
+                }
+                if ((e = launch_flow_label(a, P->storage, stream)) != hipSuccess)
+                    return hip_fail(e, "flow-label pass");
+                if (tj) {
+                    hipEventRecord(timer.ev.back(), stream);
+                    ++timed_iters;
+                }
+                cur = 1 - cur;
+            }
+            a.ell_in = a.ell_out = ell[cur];
+            a.q_in = a.q_out = q[cur];
+            if ((e = launch_flow(a, ident, nd, P->storage, stream)) != hipSuccess)
+                return hip_fail(e, "flow pass");
         } else if (want_fused) {
             a.ell_in = ell[cur];
             a.q_in = q[cur];
@@ -682,8 +724,8 @@ size_t pf_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t n_node,
     // the same sizes serve the identity (Potts) and weighted families
     const bool fused = params->kernel == PF_KERNEL_FUSED || params->kernel == PF_KERNEL_FUSED2 ||
                        (params->kernel == PF_KERNEL_AUTO &&
-                        (fused_preferred(grid->ndim, n_leaf, n_node, true, params->storage) ||
-                         fused_preferred(grid->ndim, n_leaf, n_node, false, params->storage) ||
+                        (any_fused_preferred(grid->ndim, n_leaf, n_node, true, params->storage) ||
+                         any_fused_preferred(grid->ndim, n_leaf, n_node, false, params->storage) ||
                          fused2_preferred(grid->ndim, n_leaf, n_node, true, params->storage)));
     return make_layout(*grid, n_leaf, n_node, params->storage, fused).total;
 }
@@ -698,7 +740,7 @@ int32_t pf_auto_kernel(const pf_grid *grid, int32_t n_leaf, int32_t n_node, int3
     if (lds_preferred(grid->ndim, n_leaf, n_node, (long)grid->nx * grid->ny * grid->nz, grid->batch))
         return PF_KERNEL_LDS;
     if (fused2_preferred(grid->ndim, n_leaf, n_node, id, storage)) return PF_KERNEL_FUSED2;
-    if (fused_preferred(grid->ndim, n_leaf, n_node, id, storage)) return PF_KERNEL_FUSED;
+    if (any_fused_preferred(grid->ndim, n_leaf, n_node, id, storage)) return PF_KERNEL_FUSED;
     return PF_KERNEL_TWO_PASS;
 }
 
@@ -791,8 +833,10 @@ int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const 
     if ((st = check_params(params)) != PF_OK) return st;
     if (n_labels < 2) return fail(PF_EINVAL, "the Ishikawa chain needs n_labels >= 2");
     if (n_labels > PF_MAX_LEAVES) return fail(PF_EUNSUPPORTED, "n_labels > %d", PF_MAX_LEAVES);
-    if (params->kernel == PF_KERNEL_FUSED || params->kernel == PF_KERNEL_FUSED2)
-        return fail(PF_EUNSUPPORTED, "no fused kernel for the Ishikawa chain");
+    if (params->kernel == PF_KERNEL_FUSED2 || (params->kernel == PF_KERNEL_FUSED && grid->ndim != 3))
+        return fail(PF_EUNSUPPORTED, "no %s kernel for the Ishikawa chain%s",
+                    params->kernel == PF_KERNEL_FUSED2 ? "two-iteration" : "fused",
+                    params->kernel == PF_KERNEL_FUSED2 ? "" : " in 2-D");
     Prob p;
     p.g = *grid;
     p.nl = n_labels;
@@ -806,9 +850,11 @@ int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const 
         for (int L = j + 1; L < p.nl; ++L) p.w.w[j][L] = 1.0f;
     if ((st = check_inputs_common(p, D, S, s_mode)) != PF_OK) return st;
     pf_params P2 = *params;
+    const long V = (long)p.g.nx * p.g.ny * p.g.nz;
     if (P2.kernel == PF_KERNEL_AUTO)
-        P2.kernel = lds_preferred(p.g.ndim, p.nl, p.nn, (long)p.g.nx * p.g.ny * p.g.nz, p.g.batch)
-                        ? PF_KERNEL_LDS : PF_KERNEL_TWO_PASS;
+        P2.kernel = lds_preferred(p.g.ndim, p.nl, p.nn, V, p.g.batch)            ? PF_KERNEL_LDS
+                    : any_fused_preferred(p.g.ndim, p.nl, p.nn, false, P2.storage) ? PF_KERNEL_FUSED
+                                                                               : PF_KERNEL_TWO_PASS;
     return run(p, &P2, result, static_cast<hipStream_t>(stream));
 }
 

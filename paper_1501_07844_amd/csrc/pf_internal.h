@@ -120,6 +120,18 @@ hipError_t launch_fused2(const StepArgs &a, int storage, hipStream_t s);
 bool fused2_supported(int nd, int nl, int nn, bool identity);
 bool fused2_preferred(int nd, int nl, int nn, bool identity, int storage);
 FusedGeom fused2_geometry(const StepArgs &a);
+// one pass per iteration for 3-D label graphs: the flow step of iteration k,
+// then the label step of iteration k + 1 (state between passes: labels one
+// iteration ahead of the flows), ping-pong state
+hipError_t launch_flow_label(const StepArgs &a, int storage, hipStream_t s);
+bool flow_label_supported(int nd, int nl, int nn, bool identity);
+bool flow_label_preferred(int nd, int nl, int nn, bool identity, int storage);
+// PF_KERNEL_AUTO's choice of a one-pass-per-iteration kernel (either kind)
+inline bool any_fused_preferred(int nd, int nl, int nn, bool identity, int storage) {
+    return fused_preferred(nd, nl, nn, identity, storage) ||
+           flow_label_preferred(nd, nl, nn, identity, storage);
+}
+FusedGeom flow_label_geometry(const StepArgs &a);
 // tiles of width x rows voxels, z chunks, problems (the z-marching kernels);
 // about `target` blocks, chunks of at least 16 planes
 FusedGeom tile_geometry(const StepArgs &a, int width, int rows, long target = 512);

@@ -10,7 +10,7 @@ AddressSanitizer and UBSan, driven through the C ABI with host buffers.
    reference implementation, and the fused reverse step bit for bit against
    the two-kernel one.
 
-Usage: python check.py path/to/libcpu.so [forward] [fused2] [lds] [reverse]
+Usage: python check.py path/to/libcpu.so [forward] [fused2] [lds] [flowlabel] [reverse]
 """
 import ctypes as C
 import os
@@ -145,6 +145,36 @@ def check_fused2():
     return bad
 
 
+def flow_label_cases():
+    rng = np.random.default_rng(11)
+    dag = synth.random_dag(rng, 3, 5)
+    tree = synth.hmf_tree()
+    big = synth.random_dag(rng, 0, 16)
+    tiny = synth.random_tree(rng, 1, 2)
+    return [
+        ("dag3d nl5 nn8 B2 field", synth.random_problem(4, (33, 9, 70), 3, dag, batch=2, s_mode="node_field"), 4, 0),
+        ("hmf3d nl8 nn11 shared gap2", synth.random_problem(5, (20, 13, 35), 3, tree, s_mode="shared_field"), 5, 2),
+        ("dagmf3d nl12 nn16", synth.dagmf_blobs(shape=(18, 14, 66)), 3, 0),
+        ("ishikawa3d 8 levels", synth.ishikawa_levels(shape=(17, 7, 35), n_levels=7), 3, 0),
+        ("dag3d nl16 nn16", synth.random_problem(6, (9, 8, 34), 3, big, s_mode="node_scalar"), 2, 0),
+        ("tree3d nl2 nn3 thin", synth.random_problem(7, (3, 2, 40), 3, tiny, s_mode="node_field"), 3, 0),
+    ]
+
+
+def check_flow_label():
+    """The flow-then-label pass for 3-D label graphs against the two-pass
+    kernels, bit for bit."""
+    bad = 0
+    for name, p, iters, gap_every in flow_label_cases():
+        for storage in ("fp32", "bf16", "fp16"):
+            a = solve(p, iters, "two_pass", storage, gap_every=gap_every)
+            b = solve(p, iters, "fused", storage, gap_every=gap_every)
+            same = all(np.array_equal(x, y) for x, y in zip(a[:2], b[:2])) and a[3:] == b[3:]
+            print(f"forward {name:24s} {storage}: flow-label == two-pass bitwise: {same}", flush=True)
+            bad += not same
+    return bad
+
+
 def grad(p, iters, every, bkernel, w):
     B, Z, Y, X = p.shape
     nl, nn = p.n_leaf, p.n_node
@@ -239,6 +269,8 @@ if __name__ == "__main__":
         n_bad += check_fused2()
     if not only or "lds" in only:
         n_bad += check_lds()
+    if not only or "flowlabel" in only:
+        n_bad += check_flow_label()
     if not only or "reverse" in only:
         n_bad += check_reverse()
     print("ALL OK" if n_bad == 0 else f"{n_bad} FAILED")

@@ -31,13 +31,18 @@ def main(out):
     fk = f[:f.index("template <int ND, typename T, typename F>\nhipError_t fused_bucket")]
     fk += "\n}  // namespace\n" + cut(f, "bool fused_supported(", "hipError_t launch_fused(")
     fk += "\n}  // namespace pf\n"
+    fl = open(os.path.join(SRC, "pf_flowlabel.hip")).read()
+    flk = fl[:fl.index("// ----------------------------------------------------------- dispatch ----")]
+    flk += "\n}  // namespace\n" + cut(fl, "bool flow_label_supported(", "hipError_t launch_flow_label(")
+    flk += "\n}  // namespace pf\n"
     a = open(os.path.join(SRC, "pf_adjoint.hip")).read()
     ak = a[:a.index("unsigned sblocks(size_t n)")] + "\n}  // namespace\n"
     ak += cut(a, "bool adj_fused_supported(", "hipError_t launch_adj_flow(") + "\n}  // namespace pf\n"
     # the constant address space cast has no host meaning
     d = open(os.path.join(SRC, "pf_device.h")).read().replace(
         "using cfloat = const __attribute__((address_space(4))) float;", "using cfloat = const float;")
-    for name, text in (("kernels.inc", k), ("fused.inc", fk), ("adjoint.inc", ak), ("pf_device.h", d)):
+    for name, text in (("kernels.inc", k), ("fused.inc", fk), ("flowlabel.inc", flk), ("adjoint.inc", ak),
+                       ("pf_device.h", d)):
         with open(os.path.join(out, name), "w") as fh:
             fh.write(text)
     for name in ("pf_api.cpp", "pf_internal.h"):

@@ -5,6 +5,7 @@
 // library's launchers.
 #include "kernels.inc"
 #include "fused.inc"
+#include "flowlabel.inc"
 #include "adjoint.inc"
 #include <cstdio>
 #include <cstdlib>
@@ -141,6 +142,23 @@ hipError_t launch_fused2(const StepArgs &a, int st, hipStream_t) {
         else run_grid(dim3((unsigned)g.blocks), T2THREADS, true, [&] { k_fused2<8, T>(a, g); });
         return 0;
     });
+}
+hipError_t launch_flow_label(const StepArgs &a, int st, hipStream_t) {
+    if (!flow_label_supported(3, a.nl, a.nn, false) || a.nz < 1) return 1;
+    const FusedGeom g = flow_label_geometry(a);
+    auto go = [&]<int NL, int NN, typename T>() {
+        run_grid(dim3((unsigned)g.blocks), GTHREADS, true, [&] { k_flow_label<NL, NN, T>(a, g); });
+        return 0;
+    };
+    auto by = [&]<typename T>() -> hipError_t {
+        if (a.nl <= 4 && a.nn <= 8) return go.template operator()<4, 8, T>();
+        if (a.nl <= 8 && a.nn <= 8) return go.template operator()<8, 8, T>();
+        if (a.nl <= 8 && a.nn <= 12) return go.template operator()<8, 12, T>();
+        if (a.nl <= 8 && a.nn <= 16) return go.template operator()<8, 16, T>();
+        if (a.nl <= 12 && a.nn <= 16) return go.template operator()<12, 16, T>();
+        return go.template operator()<16, 16, T>();
+    };
+    return dtype(st, by);
 }
 hipError_t launch_energy(const StepArgs &a, bool ident, int nd, int st, double *partials, double *results,
                          hipStream_t) {

@@ -72,6 +72,8 @@ def supported_kernels(p):
         ks.append("fused")
     if p.kind in ("hmf", "dagmf") and p.n_leaf <= 16 and p.n_node <= 16:
         ks.append("fused")
+    if p.kind == "ishikawa" and p.ndim == 3 and p.n_leaf <= 16:
+        ks.append("fused")
     if p.kind == "potts" and p.ndim == 3 and p.n_leaf <= 8:
         ks.append("fused2")
     V = p.shape[1] * p.shape[2] * p.shape[3]          # voxels per problem

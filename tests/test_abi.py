@@ -66,8 +66,9 @@ def test_auto_kernel_choice():
     float32 state (n_leaf + 2 n_node floats per voxel) fits in 160 KB;
     two iterations per pass for 3-D Potts up to 8 labels in every storage
     type, the one-iteration fused pass beyond with float32 state, the
-    two-pass kernels for 16-bit state beyond 8 labels, larger 2-D problems
-    and 3-D label graphs."""
+    two-pass kernels for 16-bit state beyond 8 labels and larger 2-D
+    problems; the fused pass (flow step, then the next label step) for 3-D
+    label graphs of 9 to 16 flows and at most 16 leaves with fp32 state."""
     k = pf.KERNEL
     assert pf.auto_kernel((1, 256, 256, 256), 8, 8, 3) == "fused2"
     assert pf.auto_kernel((2, 5, 7, 9), 3, 3, 3) == "fused2"
@@ -85,7 +86,13 @@ def test_auto_kernel_choice():
     assert pf.auto_kernel((8, 1, 64, 65), 3, 3, 2) == "two_pass"            # 4160 voxels > 4096
     assert pf.auto_kernel((8, 1, 64, 64), 5, 5, 2) == "two_pass"            # 61440 floats > 40960
     assert pf.auto_kernel((8, 1, 40, 40), 9, 9, 2) == "two_pass"            # more than 8 labels
-    assert pf.auto_kernel((1, 16, 16, 16), 8, 11, 3, identity=False) == "two_pass"
+    assert pf.auto_kernel((1, 16, 16, 16), 8, 11, 3, identity=False) == "fused"
+    assert pf.auto_kernel((1, 256, 512, 512), 12, 16, 3, identity=False) == "fused"
+    assert pf.auto_kernel((1, 256, 512, 512), 12, 16, 3, "bf16", identity=False) == "two_pass"
+    assert pf.auto_kernel((1, 16, 16, 16), 16, 16, 3, "fp16", identity=False) == "two_pass"
+    assert pf.auto_kernel((1, 16, 16, 16), 8, 7, 3, identity=False) == "two_pass"   # 7 flows
+    assert pf.auto_kernel((1, 16, 16, 16), 16, 30, 3, identity=False) == "two_pass"  # 30 flows
+    assert pf.auto_kernel((1, 1, 64, 64), 8, 11, 2, identity=False) == "two_pass"   # 2-D
     lib = pf.library()
     assert lib.pf_auto_kernel(C.byref(_grid()), 4, 5, 1, 0) == -1          # Potts needs n_node == n_leaf
     assert lib.pf_auto_kernel(C.byref(_grid()), 4, 4, 1, 9) == -1          # storage

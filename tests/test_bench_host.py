@@ -41,18 +41,28 @@ def test_kernel_choice_per_workload():
     assert bench._kernel_choice(pf, p, "fp32", "auto") == "fused2"
     assert bench._kernel_choice(pf, p, "bf16", "auto") == "fused2"
     assert bench._kernel_choice(pf, p, "fp32", "fused") == "fused"
-    assert bench._kernel_choice(pf, synth.hmf_ellipsoids(shape=(4, 5, 6)), "fp32", "auto") == "two_pass"
-    assert bench._kernel_choice(pf, synth.dagmf_blobs(shape=(4, 5, 6)), "fp32", "auto") == "two_pass"
+    for st, k in (("fp32", "fused"), ("bf16", "two_pass"), ("fp16", "two_pass")):
+        assert bench._kernel_choice(pf, synth.hmf_ellipsoids(shape=(4, 5, 6)), st, "auto") == k
+        assert bench._kernel_choice(pf, synth.dagmf_blobs(shape=(4, 5, 6)), st, "auto") == k
     q = synth.ishikawa_levels(shape=(4, 5, 6), n_levels=7)
-    assert bench._kernel_choice(pf, q, "fp32", "auto") == "two_pass"
+    assert bench._kernel_choice(pf, q, "fp32", "auto") == "two_pass"     # 7 flows
+    assert bench._kernel_name(q, "fused") == "k_flow_label"
+    assert bench._kernel_name(p, "fused") == "k_fused"
+    # a 2-D chain stays on the two-pass kernels (one problem: no LDS batch)
+    assert bench._kernel_choice(pf, synth.ishikawa_levels(), "fp32", "auto") == "two_pass"
 
 
-def test_traffic_record_is_gated_on_the_kernel_sources():
-    with open(os.path.join(ROOT, "profiles", "traffic_potts3d_256.json")) as fh:
+@pytest.mark.parametrize("which", sorted(bench.TRAFFIC_FILES))
+def test_traffic_record_is_gated_on_the_kernel_sources(which):
+    path = os.path.join(ROOT, "profiles", bench.TRAFFIC_FILES[which])
+    if not os.path.exists(path):
+        pytest.skip(f"no traffic record for {which}")
+    with open(path) as fh:
         rec = json.load(fh)
-    assert bench._traffic(rec["kernel"], rec["source_hash"]) == rec["bytes_per_launch"]
-    assert bench._traffic(rec["kernel"], "0" * 16) is None
-    assert bench._traffic("k_label+k_flow", rec["source_hash"]) is None
+    assert bench._traffic(which, rec["kernel"], rec["source_hash"]) == rec["bytes_per_launch"]
+    assert bench._traffic(which, rec["kernel"], "0" * 16) is None
+    other = "k_label+k_flow" if rec["kernel"] != "k_label+k_flow" else "k_flow_label"
+    assert bench._traffic(which, other, rec["source_hash"]) is None
     # the calibrated bytes are the counter values times the copy-kernel factors
     read = rec["fetch_kib_per_launch"] * 1024 * rec["fetch_factor"]
     write = rec["write_kib_per_launch"] * 1024 * rec["write_factor"]

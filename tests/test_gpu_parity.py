@@ -214,6 +214,41 @@ def test_fused_equals_two_pass_bitwise(name, storage):
     assert a.energy == b.energy and a.dual == b.dual
 
 
+FLOW_LABEL_CASES = {
+    "hmf_ellipsoids_20x36x44": (lambda: WORKLOADS["hmf_ellipsoids_20x36x44"](), 0),
+    "dagmf_blobs_18x30x38_gap7": (lambda: WORKLOADS["dagmf_blobs_18x30x38"](), 7),
+    "ishikawa_levels_20x36x44_n7": (lambda: WORKLOADS["ishikawa_levels_20x36x44_n7"](), 0),
+    "dag_nl16_nn16_B2_field": (lambda: synth.random_problem(
+        37, (9, 14, 70), 3, synth.random_dag(np.random.default_rng(37), 0, 16), batch=2,
+        s_mode="node_field"), 0),
+    "tree_nl2_nn3_shared_gap3": (lambda: synth.random_problem(
+        38, (5, 7, 133), 3, synth.random_tree(np.random.default_rng(38), 1, 2),
+        s_mode="shared_field", kind="hmf"), 3),
+    "dagmf_blobs_40x70x130_chunks": (lambda: synth.dagmf_blobs(shape=(40, 70, 130)), 0),
+}
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("name", list(FLOW_LABEL_CASES))
+def test_graph_fused_equals_two_pass_bitwise(name, storage):
+    """3-D label graphs under the fused kernel run the flow step of one
+    iteration and the label step of the next in one pass (entered with a
+    label pass, left with a flow pass around every gap check): each voxel
+    evaluates the two-pass expressions in the same order, so the states,
+    energies and duals agree bit for bit (several z chunks, ragged tiles,
+    batches, every capacity mode, odd iteration counts and gap checks)."""
+    make, gap_every = FLOW_LABEL_CASES[name]
+    p = make()
+    iters = 23
+    print(f"[flow-label] {name} {storage} gap_every={gap_every}", flush=True)
+    a = gpu_solve(p, iters, kernel="two_pass", storage=storage, return_q=True, gap_every=gap_every,
+                  gap_history_cap=8)
+    b = gpu_solve(p, iters, kernel="fused", storage=storage, return_q=True, gap_every=gap_every,
+                  gap_history_cap=8)
+    assert torch.equal(a.u, b.u) and torch.equal(a.q, b.q) and torch.equal(a.labels, b.labels)
+    assert a.energy == b.energy and a.dual == b.dual and a.gap_history == b.gap_history
+
+
 LDS_CASES = {
     "potts2d_rects_64x64": lambda: WORKLOADS["potts2d_rects_64x64"](),
     "potts2d_nl5_B3_nodefield": lambda: synth.random_potts(31, (1, 37, 70), 2, 5, batch=3,
@@ -332,8 +367,8 @@ def _solve_direct(p, iters, **kw):
 def test_unsupported_kernels_are_rejected():
     """Every documented PF_EUNSUPPORTED case returns that code through the
     C ABI (and leaves nothing half-done): two iterations per pass outside 3-D
-    Potts up to 8 labels, the fused pass for the Ishikawa chain or beyond 16
-    flows, the LDS-resident solve for 3-D or oversized 2-D problems."""
+    Potts up to 8 labels, the fused pass for the 2-D Ishikawa chain or beyond
+    16 flows, the LDS-resident solve for 3-D or oversized 2-D problems."""
     deep = synth.random_problem(201, (3, 5, 6), 3, synth.random_dag(np.random.default_rng(7), 15, 16,
                                                                     max_parents=2))
     cases = ((synth.random_potts(1, (1, 9, 11), 2, 4), "fused2", "2-D"),
