@@ -336,13 +336,15 @@ def ishikawa2d_leg(dev, reps: int = 5) -> dict:
             "energy": r.energy, "gap": r.gap}
 
 
-def counters_program(which: str = "dagmf", kernel: str = "auto") -> int:
+def counters_program(which: str = "dagmf", kernel: str = "auto",
+                     storage: str = HEADLINE_STORAGE) -> int:
     """Short program for rocprofv3 counter passes.  "dagmf": one copy of
     COPY_BYTES (the calibration kernel), then 3 iterations of the headline
     solve (3 launches of its kernel).  "potts3d": the copy, then 6 iterations
     of the 256^3 Potts solve (3 launches of k_fused2 with the AUTO choice).
     "graphs": 3 two-pass iterations of DAGMF at 128x256x256 and of Potts-3D
-    at 128^3 (fp32).  `kernel` overrides the AUTO choice."""
+    at 128^3 (fp32).  `kernel` overrides the AUTO choice, `storage` the
+    headline's state type."""
     import torch
 
     import paper_1501_07844_amd as pf
@@ -375,9 +377,9 @@ def counters_program(which: str = "dagmf", kernel: str = "auto") -> int:
         p = synth.dagmf_blobs(iters=3)
         D = torch.from_numpy(p.D).to(dev)
         r = pf.solve_dagmf(D, p.S, p.graph, c=p.c, tau=p.tau, iters=3, ndim=3, s_mode=p.s_mode,
-                           storage=HEADLINE_STORAGE, kernel=kernel, final_energy=False,
+                           storage=storage, kernel=kernel, final_energy=False,
                            return_u=False, return_labels=False)
-        choice = _kernel_choice(pf, p, HEADLINE_STORAGE, kernel)
+        choice = _kernel_choice(pf, p, storage, kernel)
     torch.cuda.synchronize()
     name = _kernel_name(p, choice)
     print(json.dumps({"counters_program": which, "iters": r.iters_done, "kernel": name,
@@ -463,14 +465,15 @@ def gap_leg(dev, p, storage: str) -> dict:
               storage=storage, gap_every=1, gap_history_cap=p.iters, final_energy=False,
               return_u=False, return_labels=False)
     g = r.gap_history
-    inc = [(k + 1, (b - a) / abs(r.energy)) for k, (a, b) in enumerate(zip(g, g[1:])) if b > a]
+    energy = r.energy
+    inc = [(k + 1, (b - a) / abs(energy)) for k, (a, b) in enumerate(zip(g, g[1:])) if b > a]
     del D, S, r
     torch.cuda.empty_cache()
     return {"workload": f"{p.name} {'x'.join(map(str, p.shape[1:]))}", "storage": storage,
             "iterations": len(g), "gap_first": g[0] if g else None, "gap_last": g[-1] if g else None,
             "increases": len(inc), "first_increase_after": inc[0][0] if inc else None,
             "max_increase_rel_energy": max((d for _, d in inc), default=0.0),
-            "min_gap_rel_energy": min(g) / abs(g[-1] if g else 1.0) if g else None}
+            "last_gap_rel_energy": g[-1] / abs(energy) if g else None}
 
 
 def main() -> int:
@@ -486,13 +489,15 @@ def main() -> int:
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--counters", nargs="?", const="dagmf", default=None,
                     choices=["dagmf", "potts3d", "graphs"])
+    ap.add_argument("--storage", default=HEADLINE_STORAGE, choices=["fp32", "bf16", "fp16"],
+                    help="state type of the --counters dagmf program")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
               "z-slab design is not built", file=sys.stderr)
         return 2
     if args.counters:
-        return counters_program(args.counters, args.kernel)
+        return counters_program(args.counters, args.kernel, args.storage)
 
     import torch
 
@@ -593,11 +598,11 @@ def main() -> int:
     return 0
 
 
-def cpu_baseline(p, nz: int = 16, iters: int = 2) -> dict:
+def cpu_baseline(p, nz: int = 64, iters: int = 2) -> dict:
     """The float64 reference implementation, as it stands, on a bounded
     sample of the headline workload: its first `nz` z-planes (all of y and
     x, the same graph, data terms and capacities), `iters` iterations (about
-    10-20 s on 16 host threads)."""
+    15 s on 16 host threads)."""
     import torch
     from oracle import pseudoflow_oracle as O
 
