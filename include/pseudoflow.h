@@ -47,6 +47,7 @@ extern "C" {
 #define PF_ABI_VERSION 3      /* 3: PF_KERNEL_LDS */
 #define PF_MAX_LEAVES 16     /* end-labels per problem */
 #define PF_MAX_NODES 32      /* non-source nodes per problem */
+#define PF_STATIC_SCRATCH_BYTES (128u << 20)   /* device scratch of solve_dagmf_static */
 
 typedef enum {
     PF_OK = 0,
@@ -202,6 +203,26 @@ int solve_hmf(const pf_grid *grid, const pf_graph *graph, const float *D, const 
  * 3-D grids, else two-pass). */
 int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
                    int32_t s_mode, const pf_params *params, pf_result *result, void *stream);
+
+/* solve_dagmf without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  The arguments and results are those of
+ * solve_dagmf, except that params->workspace must be NULL and
+ * params->workspace_bytes 0 (else PF_EINVAL), params->tape NULL and
+ * params->timing_stride 0 (else PF_EUNSUPPORTED: no tape, no HIP events).  The
+ * solver state lives in a static device array of PF_STATIC_SCRATCH_BYTES
+ * (128 MiB) that every GPU the library runs on holds until the process ends;
+ * a problem whose state and buffers need more (the workspace layout of the
+ * kernel the call runs) returns PF_ENOMEM before any device work.  The call allocates nothing: no hipMalloc, no
+ * hipFree, no HIP events.  It runs on the current device, and a non-NULL
+ * stream must belong to it (else PF_EINVAL).  Every call on a GPU shares that
+ * GPU's array and it keeps the last call's contents: the solver initialises
+ * the state it needs (warm_start = 1 continues from whatever the last call on
+ * that GPU left, meaningful only for the same problem), and calls that
+ * overlap on one GPU (other streams, other host threads) race on it. */
+int solve_dagmf_static(const pf_grid *grid, const pf_graph *graph, const float *D,
+                       const float *S, int32_t s_mode, const pf_params *params,
+                       pf_result *result, void *stream);
 
 /* Bytes of checkpoint tape for `iters` iterations recorded every
  * `ckpt_every` iterations (float32 state); 0 for invalid arguments. */

@@ -22,7 +22,8 @@ from typing import List, Optional, Sequence, Union
 import numpy as np
 
 __all__ = [
-    "solve_potts", "solve_hmf", "solve_dagmf", "solve_ishikawa", "workspace_bytes", "auto_kernel",
+    "solve_potts", "solve_hmf", "solve_dagmf", "solve_dagmf_static", "solve_ishikawa",
+    "workspace_bytes", "auto_kernel",
     "potts_layer", "dagmf_layer", "tape_bytes", "PottsFn", "DagFn",
     "SolveResult", "PseudoflowError", "library", "lib_path", "EXPORTED",
     "PF_OK", "PF_EINVAL", "PF_EGRAPH", "PF_ENOMEM", "PF_EHIP", "PF_ENONFINITE",
@@ -39,7 +40,7 @@ S_MODE = {"node_scalar": 0, "shared_field": 1, "node_field": 2}
 EXPORTED = ["pf_workspace_bytes", "solve_potts", "solve_dagmf", "solve_hmf",
             "solve_ishikawa", "pf_last_error", "pf_abi_version", "pf_tape_bytes",
             "pf_backward_workspace_bytes", "pf_potts_backward", "pf_dagmf_backward",
-            "pf_auto_kernel"]
+            "pf_auto_kernel", "solve_dagmf_static"]
 ABI_VERSION = 3
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -107,7 +108,8 @@ def library() -> C.CDLL:
         gsig = [C.POINTER(_Grid), C.POINTER(_Graph), C.c_void_p, C.c_void_p, C.c_int32,
                 C.POINTER(_Params), C.POINTER(_Result), C.c_void_p]
         for name, argt in (("solve_potts", sig), ("solve_ishikawa", sig),
-                           ("solve_dagmf", gsig), ("solve_hmf", gsig)):
+                           ("solve_dagmf", gsig), ("solve_hmf", gsig),
+                           ("solve_dagmf_static", gsig)):
             f = getattr(lib, name)
             f.restype = C.c_int
             f.argtypes = argt
@@ -230,7 +232,8 @@ def _solve(entry, D, S, n_leaf, n_node, *, graph=None, n_labels=None, c, tau, it
            s_mode=None, ndim=None, storage="fp32", kernel="auto", gap_every=0, gap_tol=0.0,
            final_energy=True, check_inputs=False, timing_stride=0, return_u=True,
            return_labels=True, return_q=False, return_ell=False, workspace=None,
-           warm_start=False, gap_history_cap=0, tape=None, ckpt_every=0) -> SolveResult:
+           warm_start=False, gap_history_cap=0, tape=None, ckpt_every=0,
+           static_scratch=False) -> SolveResult:
     torch = _torch()
     lib = library()
     _check_dev(D, "D", torch.float32)
@@ -246,15 +249,21 @@ def _solve(entry, D, S, n_leaf, n_node, *, graph=None, n_labels=None, c, tau, it
     p.timing_stride = int(timing_stride)
     if tape is not None:
         p.ckpt_every, p.tape, p.tape_bytes = int(ckpt_every), tape.data_ptr(), tape.numel()
-    need = lib.pf_workspace_bytes(C.byref(grid), n_leaf, n_node, C.byref(p))
-    if need == 0:
-        # let the solver report the precise reason
-        need = 256
-    if workspace is None or workspace.numel() < need:
-        if warm_start:
-            raise ValueError("warm_start needs the workspace of an earlier call")
-        workspace = torch.empty(need, dtype=torch.uint8, device=D.device)
-    p.workspace, p.workspace_bytes = workspace.data_ptr(), workspace.numel()
+    if static_scratch:
+        # the library's static device scratch: no workspace at all
+        if workspace is not None:
+            raise ValueError("the static-scratch solve takes no workspace")
+        p.workspace, p.workspace_bytes = None, 0
+    else:
+        need = lib.pf_workspace_bytes(C.byref(grid), n_leaf, n_node, C.byref(p))
+        if need == 0:
+            # let the solver report the precise reason
+            need = 256
+        if workspace is None or workspace.numel() < need:
+            if warm_start:
+                raise ValueError("warm_start needs the workspace of an earlier call")
+            workspace = torch.empty(need, dtype=torch.uint8, device=D.device)
+        p.workspace, p.workspace_bytes = workspace.data_ptr(), workspace.numel()
     r = _Result()
     u = labels = q = ell = None
     if return_ell:
@@ -314,6 +323,16 @@ def solve_dagmf(D, S, graph, *, c: float, tau: float, iters: int, **kw) -> Solve
     leaf in ascending node id; S one value (or field) per non-source node."""
     nl, nn = _graph_sizes(graph)
     return _solve(library().solve_dagmf, D, S, nl, nn, graph=graph, c=c, tau=tau, iters=iters, **kw)
+
+
+def solve_dagmf_static(D, S, graph, *, c: float, tau: float, iters: int, **kw) -> SolveResult:
+    """``solve_dagmf`` on the library's static device scratch (the C entry
+    point ``solve_dagmf_static``): no workspace is allocated or passed; the
+    outputs (u, labels, q, ell) are still allocated here.  For callers that
+    cannot allocate device memory; calls overlapping on one GPU race."""
+    nl, nn = _graph_sizes(graph)
+    return _solve(library().solve_dagmf_static, D, S, nl, nn, graph=graph, c=c, tau=tau,
+                  iters=iters, static_scratch=True, **kw)
 
 
 def solve_hmf(D, S, graph, *, c: float, tau: float, iters: int, **kw) -> SolveResult:

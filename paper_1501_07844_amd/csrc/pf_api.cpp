@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -55,6 +56,13 @@ Layout make_layout(const pf_grid &g, int nl, int nn, int storage, bool pingpong)
 }  // namespace pf
 
 using namespace pf;
+
+// Device scratch of solve_dagmf_static (callers that cannot allocate device
+// memory): every GPU the library runs on holds one copy until the process
+// ends.  Host code never passes this name to a kernel or a copy: it stands
+// for a host-side shadow; the device address of each GPU's copy comes from
+// hipGetSymbolAddress with that GPU current (static_scratch below).
+static __device__ __align__(256) unsigned char scratch[PF_STATIC_SCRATCH_BYTES];
 
 namespace {
 
@@ -126,7 +134,38 @@ int check_inputs_common(Prob &p, const float *D, const float *S, int s_mode) {
     return PF_OK;
 }
 
-int check_params(const pf_params *P) {
+// Device address of the static scratch on the current device, looked up
+// once per device (with that device current) and kept.  The stream, if
+// given, must belong to the current device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(hipStream_t stream, void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (stream) {
+        hipDevice_t sdev = -1;
+        if ((e = hipStreamGetDevice(stream, &sdev)) != hipSuccess) return hip_fail(e, "hipStreamGetDevice");
+        if (sdev != dev)
+            return fail(PF_EINVAL, "the stream belongs to device %d, the current device is %d", (int)sdev, dev);
+    }
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(PF_EUNSUPPORTED, "device ordinal %d outside 0..%d", dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess)
+            return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(PF_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PF_OK;
+}
+
+int check_params(const pf_params *P, bool static_ws = false) {
     if (!P) return fail(PF_EINVAL, "params is NULL");
     if (P->iters < 0) return fail(PF_EINVAL, "iters must be >= 0 (got %d)", P->iters);
     if (!(P->c > 0.f) || !std::isfinite(P->c)) return fail(PF_EINVAL, "c must be finite and > 0");
@@ -139,6 +178,15 @@ int check_params(const pf_params *P) {
     if (P->gap_every < 0) return fail(PF_EINVAL, "gap_every must be >= 0");
     if (!(P->gap_tol >= 0.0)) return fail(PF_EINVAL, "gap_tol must be >= 0");
     if (P->timing_stride < 0) return fail(PF_EINVAL, "timing_stride must be >= 0");
+    if (static_ws) {
+        if (P->workspace || P->workspace_bytes)
+            return fail(PF_EINVAL, "the static-scratch solve takes no workspace "
+                                   "(workspace must be NULL and workspace_bytes 0)");
+        if (P->tape) return fail(PF_EUNSUPPORTED, "the static-scratch solve records no tape");
+        if (P->timing_stride)
+            return fail(PF_EUNSUPPORTED, "the static-scratch solve times no launches (timing_stride 0)");
+        return PF_OK;
+    }
     if (!P->workspace) return fail(PF_EINVAL, "workspace is NULL");
     if (!aligned(P->workspace, 256)) return fail(PF_EINVAL, "workspace is not 256-byte aligned");
     return PF_OK;
@@ -267,7 +315,7 @@ int check_tape(const Prob &p, const pf_params *P) {
     return PF_OK;
 }
 
-int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
+int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream, bool static_ws = false) {
     int tst = check_tape(p, P);
     if (tst != PF_OK) return tst;
     if (P->tape && (P->kernel == PF_KERNEL_FUSED || P->kernel == PF_KERNEL_FUSED2 ||
@@ -295,7 +343,10 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
     const bool want_fl = want_fused && !want_fused2 &&
                          flow_label_supported(p.g.ndim, p.nl, p.nn, p.ident);
     const Layout lay = make_layout(p.g, p.nl, p.nn, P->storage, want_fused);
-    if (P->workspace_bytes < lay.total)
+    if (static_ws && lay.total > (size_t)PF_STATIC_SCRATCH_BYTES)
+        return fail(PF_ENOMEM, "the problem needs %zu bytes of device scratch, more than the %zu "
+                               "bytes of the static scratch", lay.total, (size_t)PF_STATIC_SCRATCH_BYTES);
+    if (!static_ws && P->workspace_bytes < lay.total)
         return fail(PF_ENOMEM, "workspace of %zu bytes < %zu needed", P->workspace_bytes, lay.total);
     if (!R) return fail(PF_EINVAL, "result is NULL");
     if ((R->u && !aligned(R->u, 4)) || (R->labels && !aligned(R->labels, 4)) ||
@@ -304,6 +355,12 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream) {
     if (R->gap_history && R->gap_history_cap < 0) return fail(PF_EINVAL, "gap_history_cap < 0");
 
     char *ws = static_cast<char *>(P->workspace);
+    if (static_ws) {
+        void *sp = nullptr;
+        const int st = static_scratch(stream, &sp);
+        if (st != PF_OK) return st;
+        ws = static_cast<char *>(sp);
+    }
     double *results = reinterpret_cast<double *>(ws + lay.results);
     int32_t *flags = reinterpret_cast<int32_t *>(ws + lay.flags);
     double *partials = reinterpret_cast<double *>(ws + lay.partials);
@@ -761,15 +818,20 @@ int solve_potts(const pf_grid *grid, int32_t n_labels, const float *D, const flo
 
 static int solve_graph(const pf_grid *grid, const pf_graph *graph, bool tree, const float *D,
                        const float *S, int32_t s_mode, const pf_params *params,
-                       pf_result *result, void *stream) {
+                       pf_result *result, void *stream, bool static_ws = false) {
     int st;
     if ((st = check_grid(grid)) != PF_OK) return st;
-    if ((st = check_params(params)) != PF_OK) return st;
+    if ((st = check_params(params, static_ws)) != PF_OK) return st;
     Prob p;
     p.g = *grid;
     if ((st = build_graph(graph, tree, p)) != PF_OK) return st;
     if ((st = check_inputs_common(p, D, S, s_mode)) != PF_OK) return st;
-    return run(p, params, result, static_cast<hipStream_t>(stream));
+    return run(p, params, result, static_cast<hipStream_t>(stream), static_ws);
+}
+
+int solve_dagmf_static(const pf_grid *grid, const pf_graph *graph, const float *D, const float *S,
+                       int32_t s_mode, const pf_params *params, pf_result *result, void *stream) {
+    return solve_graph(grid, graph, false, D, S, s_mode, params, result, stream, true);
 }
 
 int solve_dagmf(const pf_grid *grid, const pf_graph *graph, const float *D, const float *S,
