@@ -17,8 +17,9 @@ two-iteration kernel; the per-iteration kernel rates of every workload
 (Potts 3-D, HMF, DAGMF and an Ishikawa chain scaled to 128 x 256 x 256 with 8
 ordered labels; float32, bf16 and fp16 state), whole-solve rates of the two
 small 2-D cases (Potts and Ishikawa) and of a batch of 256 of the Potts case;
-the primal-dual gap after every iteration of the Potts and DAGMF solves; a
-plain device copy as the achievable bandwidth; the cost of the
+the primal-dual gap after every iteration of the Potts and DAGMF solves; the
+full-flow counterpart against the pseudo-flow solver on the Potts workload
+(state memory, time per iteration, gap reached); a plain device copy as the achievable bandwidth; the cost of the
 differentiable solve; and the float64 reference implementation timed on a
 bounded sample on the host.
 
@@ -453,6 +454,59 @@ def potts3d_leg(dev, n: int, steps: int = 2) -> dict:
     return out
 
 
+FULLFLOW_C, FULLFLOW_TAU = 1.0, 0.11     # frozen on the reference at reduced size
+
+
+def fullflow_leg(dev, n: int) -> dict:
+    """The full-flow counterpart against the pseudo-flow solver on the 256^3
+    Potts workload (8 labels, float32, 500 iterations): device state bytes
+    (each solver's workspace; the pseudo-flow two-pass layout and the
+    ping-ponged layout of its AUTO kernel), per-iteration kernel time (HIP
+    events around every iteration of a 20-iteration solve after a warm-up),
+    algorithmic bytes per iteration, and the energy and relative gap each
+    reaches in 500 iterations."""
+    import torch
+
+    import paper_1501_07844_amd as pf
+    from paper_1501_07844_amd import synth
+    p = synth.potts3d_voronoi(n=n, iters=POTTS_ITERS)
+    D, S = _inputs(p, dev)
+    kw = dict(ndim=3, s_mode=p.s_mode, final_energy=True, return_u=False, return_labels=False)
+    ff = pf.solve_potts_fullflow(D, S, c=FULLFLOW_C, tau=FULLFLOW_TAU, iters=POTTS_ITERS, **kw)
+    r = pf.solve_potts_fullflow(D, S, c=FULLFLOW_C, tau=FULLFLOW_TAU, iters=20,
+                                workspace=ff.workspace, timing_stride=1, **kw)
+    ff_ms = r.kernel_ms / max(r.kernel_timed, 1)
+    ps = pf.solve_potts(D, S, c=p.c, tau=p.tau, iters=POTTS_ITERS, kernel="auto", **kw)
+    pr = pf.solve_potts(D, S, c=p.c, tau=p.tau, iters=20, kernel="auto", workspace=ps.workspace,
+                        timing_stride=1, **kw)
+    ps_ms = pr.kernel_ms / max(pr.kernel_timed, 1)
+    nl, nd, V = p.n_leaf, 3, p.voxels
+    ff_bytes = pf.fullflow_workspace_bytes(p.shape, nl, nd)
+    ps_two = pf.workspace_bytes(p.shape, nl, nl, nd, kernel="two_pass")
+    ps_auto = pf.workspace_bytes(p.shape, nl, nl, nd, kernel="auto")
+    d_bytes = 4 * nl * V
+    ff_alg = 4 * (nl * (3 * nd + 5) + 3)          # bytes per voxel and iteration (two passes)
+    out = {"workload": f"potts3d_voronoi {n}x{n}x{n}, 8 labels, fp32, {POTTS_ITERS} iterations",
+           "fullflow": {"c": FULLFLOW_C, "tau": FULLFLOW_TAU, "state_bytes": ff_bytes,
+                        "state_fields_per_voxel": (nd + 2) * nl + 1,
+                        "ms_per_iter": round(ff_ms, 4), "alg_bytes_per_voxel_iter": ff_alg,
+                        "alg_GBs": round(ff_alg * V / (ff_ms * 1e-3) / 1e9, 1),
+                        "energy": ff.energy, "rel_gap": ff.gap / abs(ff.energy)},
+           "pseudoflow": {"c": p.c, "tau": p.tau, "state_bytes_two_pass": ps_two,
+                          "state_bytes_auto": ps_auto, "state_fields_per_voxel": (nd + 1) * nl,
+                          "ms_per_iter": round(ps_ms, 4), "kernel": "k_fused2 (two iterations per launch)",
+                          "energy": ps.energy, "rel_gap": ps.gap / abs(ps.energy)},
+           "data_term_bytes": d_bytes,
+           "state_saving": round(1 - ps_two / ff_bytes, 4),
+           "saving_with_data_terms": round(1 - (ps_two + d_bytes) / (ff_bytes + d_bytes), 4),
+           "speedup_per_iteration": round(ff_ms / ps_ms, 3)}
+    print(f"[bench] full flow {ff_ms:.3f} ms/iter ({ff_bytes / 1e9:.2f} GB state), pseudo-flow "
+          f"{ps_ms:.3f} ms/iter ({ps_two / 1e9:.2f} GB)", file=sys.stderr, flush=True)
+    del D, S, ff, r, ps, pr
+    torch.cuda.empty_cache()
+    return out
+
+
 def gap_leg(dev, p, storage: str) -> dict:
     """The primal-dual gap after every iteration of a whole solve (not
     timed): how often it increases and by how much relative to the energy."""
@@ -580,6 +634,7 @@ def main() -> int:
                                 "rel_energy_at_budget": g["rel_energy_full_vs_fp32"],
                                 "iterations": g["iterations_full"]}
                                for g in legs if g["storage"] == "bf16"]
+        out["fullflow_vs_pseudoflow"] = fullflow_leg(dev, args.n)
         out["gap_behaviour"] = [gap_leg(dev, synth.potts3d_voronoi(n=args.n, iters=POTTS_ITERS), "fp32"),
                                 gap_leg(dev, p, HEADLINE_STORAGE)]
         out["potts2d"] = potts2d_leg(dev)

@@ -224,6 +224,33 @@ int solve_dagmf_static(const pf_grid *grid, const pf_graph *graph, const float *
                        const float *S, int32_t s_mode, const pf_params *params,
                        pf_result *result, void *stream);
 
+/* Full-flow counterpart of solve_potts, kept to measure what the pseudo-flow
+ * representation saves (Potts primal max-flow and primal-dual models, section
+ * "Pseudo-Flow Approach to the Potts Model"; the paper names the full-flow
+ * method but prints no algorithm for it).  Every variable of the primal-dual
+ * model is explicit: spatial flows q_L, source flow p_S, sink flows
+ * p_L <= D_L, and the labels u_L as the multipliers of flow conservation
+ * div q_L - p_S + p_L = 0.  One iteration of the augmented Lagrangian with
+ * penalty c = params->c and spatial step tau = params->tau:
+ *   q_L <- Proj_{|q_L| <= S_L}(q_L + tau grad(div q_L - p_S + p_L - u_L/c))
+ *   p_L  = min(D_L, p_S - div q_L + u_L/c)
+ *   p_S <- (1/n) sum_L (div q_L + p_L - u_L/c) + 1/(n c)
+ *   u_L <- u_L - c (div q_L - p_S + p_L)
+ * from q = 0, p_S = p_L = min_L D_L, u = 1/n_labels.  State (float32 only,
+ * in the caller's workspace of pf_fullflow_workspace_bytes): q, u, p_S and
+ * the flow-step driver div q_L - p_S + p_L - u_L/c, (ndim + 2) n + 1 fields
+ * per voxel.  Energy and dual (float64): E of u clipped at 0 and renormalised
+ * per voxel, P = sum_x min_L (D_L + div q_L); max_simplex_err is
+ * max |sum_L u_L - 1|.  result->u receives u as it is (it need not be >= 0
+ * before convergence), result->labels its argmax, result->q the spatial
+ * flows; result->ell must be NULL.  At most 16 labels; storage PF_FP32 and
+ * kernel PF_KERNEL_AUTO or PF_KERNEL_TWO_PASS, no tape (PF_EUNSUPPORTED
+ * otherwise).  Other arguments, errors, streams and timing as solve_potts. */
+size_t pf_fullflow_workspace_bytes(const pf_grid *grid, int32_t n_labels);
+int solve_potts_fullflow(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
+                         int32_t s_mode, const pf_params *params, pf_result *result,
+                         void *stream);
+
 /* Bytes of checkpoint tape for `iters` iterations recorded every
  * `ckpt_every` iterations (float32 state); 0 for invalid arguments. */
 size_t pf_tape_bytes(const pf_grid *grid, int32_t n_leaf, int32_t n_node, int32_t iters,

@@ -23,6 +23,7 @@ import numpy as np
 
 __all__ = [
     "solve_potts", "solve_hmf", "solve_dagmf", "solve_dagmf_static", "solve_ishikawa",
+    "solve_potts_fullflow", "fullflow_workspace_bytes",
     "workspace_bytes", "auto_kernel",
     "potts_layer", "dagmf_layer", "tape_bytes", "PottsFn", "DagFn",
     "SolveResult", "PseudoflowError", "library", "lib_path", "EXPORTED",
@@ -40,7 +41,8 @@ S_MODE = {"node_scalar": 0, "shared_field": 1, "node_field": 2}
 EXPORTED = ["pf_workspace_bytes", "solve_potts", "solve_dagmf", "solve_hmf",
             "solve_ishikawa", "pf_last_error", "pf_abi_version", "pf_tape_bytes",
             "pf_backward_workspace_bytes", "pf_potts_backward", "pf_dagmf_backward",
-            "pf_auto_kernel", "solve_dagmf_static"]
+            "pf_auto_kernel", "solve_dagmf_static", "solve_potts_fullflow",
+            "pf_fullflow_workspace_bytes"]
 ABI_VERSION = 3
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -101,6 +103,8 @@ def library() -> C.CDLL:
         lib = C.CDLL(path)
         lib.pf_workspace_bytes.restype = C.c_size_t
         lib.pf_workspace_bytes.argtypes = [C.POINTER(_Grid), C.c_int32, C.c_int32, C.POINTER(_Params)]
+        lib.pf_fullflow_workspace_bytes.restype = C.c_size_t
+        lib.pf_fullflow_workspace_bytes.argtypes = [C.POINTER(_Grid), C.c_int32]
         lib.pf_auto_kernel.restype = C.c_int32
         lib.pf_auto_kernel.argtypes = [C.POINTER(_Grid), C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         sig = [C.POINTER(_Grid), C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
@@ -109,7 +113,7 @@ def library() -> C.CDLL:
                 C.POINTER(_Params), C.POINTER(_Result), C.c_void_p]
         for name, argt in (("solve_potts", sig), ("solve_ishikawa", sig),
                            ("solve_dagmf", gsig), ("solve_hmf", gsig),
-                           ("solve_dagmf_static", gsig)):
+                           ("solve_dagmf_static", gsig), ("solve_potts_fullflow", sig)):
             f = getattr(lib, name)
             f.restype = C.c_int
             f.argtypes = argt
@@ -233,7 +237,7 @@ def _solve(entry, D, S, n_leaf, n_node, *, graph=None, n_labels=None, c, tau, it
            final_energy=True, check_inputs=False, timing_stride=0, return_u=True,
            return_labels=True, return_q=False, return_ell=False, workspace=None,
            warm_start=False, gap_history_cap=0, tape=None, ckpt_every=0,
-           static_scratch=False) -> SolveResult:
+           static_scratch=False, fullflow=False) -> SolveResult:
     torch = _torch()
     lib = library()
     _check_dev(D, "D", torch.float32)
@@ -255,7 +259,8 @@ def _solve(entry, D, S, n_leaf, n_node, *, graph=None, n_labels=None, c, tau, it
             raise ValueError("the static-scratch solve takes no workspace")
         p.workspace, p.workspace_bytes = None, 0
     else:
-        need = lib.pf_workspace_bytes(C.byref(grid), n_leaf, n_node, C.byref(p))
+        need = (lib.pf_fullflow_workspace_bytes(C.byref(grid), n_leaf) if fullflow
+                else lib.pf_workspace_bytes(C.byref(grid), n_leaf, n_node, C.byref(p)))
         if need == 0:
             # let the solver report the precise reason
             need = 256
@@ -333,6 +338,22 @@ def solve_dagmf_static(D, S, graph, *, c: float, tau: float, iters: int, **kw) -
     nl, nn = _graph_sizes(graph)
     return _solve(library().solve_dagmf_static, D, S, nl, nn, graph=graph, c=c, tau=tau,
                   iters=iters, static_scratch=True, **kw)
+
+
+def fullflow_workspace_bytes(shape, n_labels: int, ndim: int) -> int:
+    """Bytes of workspace of the full-flow Potts solver for a [B, Z, Y, X] problem."""
+    B, Z, Y, X = shape
+    return int(library().pf_fullflow_workspace_bytes(C.byref(_Grid(B, ndim, Z, Y, X)), n_labels))
+
+
+def solve_potts_fullflow(D, S, *, c: float, tau: float, iters: int, **kw) -> SolveResult:
+    """Full-flow counterpart of ``solve_potts`` (explicit source, sink and
+    spatial flows, the labels as multipliers; ``c`` the penalty of the
+    augmented Lagrangian, ``tau`` the spatial-flow step).  float32 state;
+    ``u`` holds the multipliers as they are."""
+    n = int(D.shape[1])
+    return _solve(library().solve_potts_fullflow, D, S, n, n, n_labels=n, c=c, tau=tau,
+                  iters=iters, fullflow=True, **kw)
 
 
 def solve_hmf(D, S, graph, *, c: float, tau: float, iters: int, **kw) -> SolveResult:

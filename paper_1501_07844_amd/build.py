@@ -18,7 +18,8 @@ LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libpseudoflow.so")
 BUILDDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["pf_kernels.hip", "pf_fused.hip", "pf_flowlabel.hip", "pf_adjoint.hip", "pf_api.cpp"]
+SOURCES = ["pf_kernels.hip", "pf_fused.hip", "pf_flowlabel.hip", "pf_fullflow.hip", "pf_adjoint.hip",
+           "pf_api.cpp"]
 
 COMMON = [
     "--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC",

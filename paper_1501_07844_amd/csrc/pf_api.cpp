@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "pf_fullflow.h"
 #include "pf_internal.h"
 #include "pseudoflow.h"
 
@@ -886,6 +887,165 @@ int pf_dagmf_backward(const pf_grid *grid, const pf_graph *graph, const float *D
     if ((st = build_graph(graph, false, p)) != PF_OK) return st;
     if ((st = check_inputs_common(p, D, S, s_mode)) != PF_OK) return st;
     return run_backward(p, params, grad_ell, grad_D, grad_S, static_cast<hipStream_t>(stream));
+}
+
+size_t pf_fullflow_workspace_bytes(const pf_grid *grid, int32_t n_labels) {
+    if (check_grid(grid) != PF_OK || !ff_supported(grid->ndim, n_labels)) return 0;
+    return ff_layout(*grid, n_labels).total;
+}
+
+int solve_potts_fullflow(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
+                         int32_t s_mode, const pf_params *params, pf_result *R, void *stream_) {
+    int st;
+    if ((st = check_grid(grid)) != PF_OK) return st;
+    if ((st = check_params(params)) != PF_OK) return st;
+    const pf_params *P = params;
+    if (n_labels < 1) return fail(PF_EINVAL, "n_labels must be >= 1");
+    if (!ff_supported(grid->ndim, n_labels))
+        return fail(PF_EUNSUPPORTED, "the full-flow solver takes at most 16 labels");
+    if (P->storage != PF_FP32) return fail(PF_EUNSUPPORTED, "the full-flow solver keeps float32 state");
+    if (P->kernel != PF_KERNEL_AUTO && P->kernel != PF_KERNEL_TWO_PASS)
+        return fail(PF_EUNSUPPORTED, "the full-flow solver runs its two kernels per iteration only");
+    if (P->tape) return fail(PF_EUNSUPPORTED, "the full-flow solver records no tape");
+    Prob p;
+    p.g = *grid;
+    p.nl = p.nn = n_labels;
+    p.ident = true;
+    if ((st = check_inputs_common(p, D, S, s_mode)) != PF_OK) return st;
+    const FFLayout lay = ff_layout(p.g, n_labels);
+    if (P->workspace_bytes < lay.total)
+        return fail(PF_ENOMEM, "workspace of %zu bytes < %zu needed", P->workspace_bytes, lay.total);
+    if (!R) return fail(PF_EINVAL, "result is NULL");
+    if (R->ell) return fail(PF_EUNSUPPORTED, "the full-flow state holds no log-labels (ell must be NULL)");
+    if ((R->u && !aligned(R->u, 4)) || (R->labels && !aligned(R->labels, 4)) || (R->q && !aligned(R->q, 4)))
+        return fail(PF_EINVAL, "output pointers must be 4-byte aligned");
+    if (R->gap_history && R->gap_history_cap < 0) return fail(PF_EINVAL, "gap_history_cap < 0");
+    hipStream_t stream = static_cast<hipStream_t>(stream_);
+
+    char *ws = static_cast<char *>(P->workspace);
+    double *results = reinterpret_cast<double *>(ws + lay.results);
+    double *partials = reinterpret_cast<double *>(ws + lay.partials);
+    float *consts = reinterpret_cast<float *>(ws + lay.consts);
+    const int nd = p.g.ndim;
+    StepArgs a{};
+    a.nx = p.g.nx;
+    a.ny = p.g.ny;
+    a.nz = p.g.nz;
+    a.V = p.g.nx * p.g.ny * p.g.nz;
+    a.B = p.g.batch;
+    a.nl = a.nn = n_labels;
+    a.inv_c = 1.0f / P->c;
+    a.ctau = P->tau;
+    a.s_mode = p.s_mode;
+    a.D = p.D;
+    a.S = p.S;
+    a.W = consts + PF_MAX_NODES;
+    if (p.s_mode == PF_S_NODE_SCALAR) {
+        a.Sp = consts;
+        a.s_sb = 0, a.s_sa = 1, a.s_sv = 0;
+    } else if (p.s_mode == PF_S_SHARED_FIELD) {
+        a.Sp = p.S;
+        a.s_sb = a.V, a.s_sa = 0, a.s_sv = 1;
+    } else {
+        a.Sp = p.S;
+        a.s_sb = (int64_t)p.nn * a.V, a.s_sa = a.V, a.s_sv = 1;
+    }
+    FFArgs f{};
+    f.q = reinterpret_cast<float *>(ws + lay.q);
+    f.u = reinterpret_cast<float *>(ws + lay.u);
+    f.w = reinterpret_cast<float *>(ws + lay.w);
+    f.pS = reinterpret_cast<float *>(ws + lay.pS);
+    f.c = P->c;
+    f.tau = P->tau;
+
+    R->iters_done = 0;
+    R->gap_history_len = 0;
+    R->energy = R->dual = R->gap = NAN;
+    R->max_simplex_err = R->max_flow_excess = NAN;
+    R->kernel_ms = 0.0;
+    R->kernel_timed = 0;
+    hipError_t e;
+    {
+        ConstBlock cb{};
+        std::memcpy(cb.s_node, p.s_node, sizeof cb.s_node);
+        if ((e = launch_upload(cb, consts, stream)) != hipSuccess) return hip_fail(e, "upload");
+    }
+    if (P->check_inputs) {
+        int32_t *flags = reinterpret_cast<int32_t *>(ws + lay.results + 64);
+        if ((e = launch_check(a, flags, stream)) != hipSuccess) return hip_fail(e, "input check");
+        int32_t flag = 0;
+        if ((e = hipMemcpyAsync(&flag, flags, sizeof flag, hipMemcpyDeviceToHost, stream)) != hipSuccess)
+            return hip_fail(e, "input check copy");
+        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "input check sync");
+        if (flag & 1) return fail(PF_ENONFINITE, "D holds NaN or Inf");
+        if (flag & 2) return fail(PF_ENONFINITE, "S holds NaN, Inf or a negative value");
+    }
+    if (!P->warm_start && (e = launch_ff_init(a, f, nd, stream)) != hipSuccess)
+        return hip_fail(e, "full-flow init");
+    auto evaluate = [&](double out[4]) -> int {
+        hipError_t err = launch_ff_energy(a, f, nd, partials, results, stream);
+        if (err != hipSuccess) return hip_fail(err, "full-flow energy");
+        if ((err = hipMemcpyAsync(out, results, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                                  stream)) != hipSuccess)
+            return hip_fail(err, "energy copy");
+        if ((err = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(err, "energy sync");
+        if (!std::isfinite(out[0]) || !std::isfinite(out[1]))
+            return fail(PF_ENONFINITE, "non-finite energy/dual after %d iterations", R->iters_done);
+        return PF_OK;
+    };
+    Timer timer;
+    int timed = 0;
+    for (int it = 0; it < P->iters; ++it) {
+        const bool tj = P->timing_stride > 0 && it % P->timing_stride == 0;
+        if (tj) {
+            hipEvent_t e0, e1;
+            if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+                return fail(PF_EHIP, "hipEventCreate failed");
+            timer.ev.push_back(e0);
+            timer.ev.push_back(e1);
+            hipEventRecord(e0, stream);
+        }
+        if ((e = launch_ff_iteration(a, f, nd, stream)) != hipSuccess)
+            return hip_fail(e, "full-flow iteration");
+        if (tj) {
+            hipEventRecord(timer.ev.back(), stream);
+            ++timed;
+        }
+        R->iters_done = it + 1;
+        if (P->gap_every > 0 && (it + 1) % P->gap_every == 0) {
+            double r[4];
+            if ((st = evaluate(r)) != PF_OK) return st;
+            const double gap = r[0] - r[1];
+            if (R->gap_history && R->gap_history_len < R->gap_history_cap)
+                R->gap_history[R->gap_history_len++] = gap;
+            R->energy = r[0], R->dual = r[1], R->gap = gap;
+            R->max_simplex_err = r[2], R->max_flow_excess = r[3];
+            if (P->gap_tol > 0.0 && gap <= P->gap_tol * std::fabs(r[0])) break;
+        }
+    }
+    if (P->final_energy) {
+        double r[4];
+        if ((st = evaluate(r)) != PF_OK) return st;
+        R->energy = r[0], R->dual = r[1], R->gap = r[0] - r[1];
+        R->max_simplex_err = r[2], R->max_flow_excess = r[3];
+    }
+    if ((R->u || R->labels || R->q) &&
+        (e = launch_ff_export(a, f, nd, R->u, R->labels, R->q, stream)) != hipSuccess)
+        return hip_fail(e, "full-flow export");
+    if (!timer.ev.empty()) {
+        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "timing sync");
+        double ms = 0.0;
+        for (size_t i = 0; i + 1 < timer.ev.size(); i += 2) {
+            float t = 0.f;
+            if ((e = hipEventElapsedTime(&t, timer.ev[i], timer.ev[i + 1])) != hipSuccess)
+                return hip_fail(e, "hipEventElapsedTime");
+            ms += t;
+        }
+        R->kernel_ms = ms;
+        R->kernel_timed = timed;
+    }
+    g_err.clear();
+    return PF_OK;
 }
 
 int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
