@@ -93,6 +93,7 @@ struct Prob {
     const float *S = nullptr;
     int s_mode = 0;
     bool ident = true;
+    bool tail = false;       // the last nl nodes are the end-labels, in order
     GraphW w{};
     float s_node[PF_MAX_NODES] = {};
 };
@@ -273,6 +274,8 @@ int build_graph(const pf_graph *G, bool tree_only, Prob &p) {
     p.nl = (int)leaves.size();
     p.nn = n - 1;
     p.ident = false;
+    p.tail = true;
+    for (int L = 0; L < p.nl; ++L) p.tail = p.tail && leaves[L] == n - p.nl + L;
     std::memset(&p.w, 0, sizeof p.w);
     p.w.nl = p.nl;
     p.w.nn = p.nn;
@@ -498,7 +501,7 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream, bool stat
                     timer.ev.push_back(e1);
                     hipEventRecord(e0, stream);
                 }
-                if ((e = launch_flow_label(a, P->storage, stream)) != hipSuccess)
+                if ((e = launch_flow_label(a, P->storage, p.tail, stream)) != hipSuccess)
                     return hip_fail(e, "flow-label pass");
                 if (tj) {
                     hipEventRecord(timer.ev.back(), stream);

@@ -41,23 +41,47 @@ namespace {
 using namespace dev;
 
 constexpr int GX = 64;                     // tile width (one wavefront per row)
-constexpr int GY = 8;                      // owned tile rows
+constexpr int GY = 8;                      // owned tile rows (4: 1.17-1.32x slower)
 constexpr int GTHREADS = GX * (GY + 2);    // owned rows, the halo row, the halo column
+
+// Flow slots of a build: NI dense slots (slot s is node s, its path-weight
+// row W[s][*] read from the constants), then, when TAIL, NLMAX identity slots:
+// slot NI + L is node ni + L with ni = nn - nl, the end-label L itself, whose
+// row is the unit vector of L.  The host takes TAIL only for graphs whose
+// last nl nodes are the end-labels in order (every internal node numbered
+// before every leaf), and with 16-bit state only for an even ni (a packed
+// pair of flows never straddles the two kinds).  An identity slot's grad U is
+// grad u_L and its excess goes to d_L alone: the values the dense products
+// give (every other term is an exact zero), without the products.
+template <int NLMAX, int NI, bool TAIL>
+struct Slots {
+    static constexpr int N = TAIL ? NI + NLMAX : NI;
+    static __device__ __forceinline__ bool tail(int s) { return TAIL && s >= NI; }
+    static __device__ __forceinline__ int node(const StepArgs &a, int s) {
+        return tail(s) ? (a.nn - a.nl) + (s - NI) : s;
+    }
+    static __device__ __forceinline__ bool valid(const StepArgs &a, int s) {
+        return tail(s) ? s - NI < a.nl : s < (TAIL ? a.nn - a.nl : a.nn);
+    }
+};
 
 // Flow step of iteration k at voxel (x, y, z): the labels of iteration k at
 // the voxel (returned in e0, as stored) and at x + e_k, the old flows at the
-// voxel and the capacities; returns the new flows after a round trip
-// through the storage type (what a later load returns; 0 past the last
-// flow) and stores them when `store`.
-template <int NLMAX, int NNMAX, typename T>
+// voxel and the capacities; returns the new flows of every slot after a
+// round trip through the storage type (what a later load returns; 0 in a
+// slot past the graph) and stores them when `store`.
+template <int NLMAX, int NI, bool TAIL, typename T>
 __device__ __forceinline__ void flow_point(const StepArgs &a, int b, int x, int y, int z, bool store,
-                                           float (&e0)[NLMAX], float (&pr)[NNMAX][3]) {
+                                           float (&e0)[NLMAX],
+                                           float (&pr)[Slots<NLMAX, NI, TAIL>::N][3]) {
+    using SL = Slots<NLMAX, NI, TAIL>;
+    constexpr int NS = SL::N;
     const size_t V = (size_t)a.V;
     const unsigned uv = (unsigned)((z * a.ny + y) * a.nx + x);
     const bool h[3] = {x < a.nx - 1, y < a.ny - 1, z < a.nz - 1};
     const unsigned off[3] = {h[0] ? 1u : 0u, h[1] ? (unsigned)a.nx : 0u,
                              h[2] ? (unsigned)(a.nx * a.ny) : 0u};
-    float en[NLMAX][3], qv[NNMAX][3], sv[NNMAX];
+    float en[NLMAX][3], qv[NS][3], sv[NS];
 #pragma unroll
     for (int L = 0; L < NLMAX; ++L) {
         e0[L] = ld_ell<T>(a.ell_in, b, a.nl, L, V, uv);
@@ -65,10 +89,11 @@ __device__ __forceinline__ void flow_point(const StepArgs &a, int b, int x, int 
         for (int k = 0; k < 3; ++k) en[L][k] = ld_ell<T>(a.ell_in, b, a.nl, L, V, uv + off[k]);
     }
 #pragma unroll
-    for (int A = 0; A < NNMAX; ++A) {
+    for (int s = 0; s < NS; ++s) {
+        const int A = SL::valid(a, s) ? SL::node(a, s) : a.nn - 1;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) qv[A][k] = ld_q<T, 3>(a.q_in, b, a.nn, A, k, V, uv);
-        sv[A] = smooth(a, b, A < a.nn ? A : a.nn - 1, (int)uv);
+        for (int k = 0; k < 3; ++k) qv[s][k] = ld_q<T, 3>(a.q_in, b, a.nn, A, k, V, uv);
+        sv[s] = smooth(a, b, A, (int)uv);
     }
     float gu[NLMAX][3];
 #pragma unroll
@@ -77,34 +102,58 @@ __device__ __forceinline__ void flow_point(const StepArgs &a, int b, int x, int 
 #pragma unroll
         for (int k = 0; k < 3; ++k) gu[L][k] = h[k] ? __expf(en[L][k]) - u0 : 0.f;
     }
+    // slot pairs, stored as they are formed; with 16-bit state a slot pair
+    // is a node pair (2P, 2P + 1) of one packed word (NI and ni are even)
 #pragma unroll
-    for (int A = 0; A < NNMAX; A += 2) {
+    for (int s = 0; s < NS; s += 2) {
         float p[2][3];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             p[j][0] = p[j][1] = p[j][2] = 0.f;
-            if (A + j < a.nn) {
+            if (SL::valid(a, s + j)) {
                 float G[3];
-                grad_U<3, NLMAX, false>(a, A + j, gu, G);
-                flow_project<3>(a, qv[A + j], G, h, sv[A + j], p[j]);
+                if (SL::tail(s + j)) {
+                    const int L = s + j - NI;
+                    G[0] = gu[L][0], G[1] = gu[L][1], G[2] = gu[L][2];
+                } else {
+                    grad_U<3, NLMAX, false>(a, s + j, gu, G);
+                }
+                flow_project<3>(a, qv[s + j], G, h, sv[s + j], p[j]);
             }
         }
-        if (store && A < a.nn) {
+        if (store) {
+            if constexpr (kPacked<T>) {
+                if (SL::valid(a, s)) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) st_q2<T, 3>(a.q_out, b, a.nn, A, k, V, uv, p[0][k], p[1][k]);
+                    for (int k = 0; k < 3; ++k)
+                        st_q2<T, 3>(a.q_out, b, a.nn, SL::node(a, s), k, V, uv, p[0][k], p[1][k]);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    if (SL::valid(a, s + j)) {
+#pragma unroll
+                        for (int k = 0; k < 3; ++k)
+                            sto(field_w<float>(a.q_out, b, a.nn * 3, SL::node(a, s + j) * 3 + k, V), uv,
+                                p[j][k]);
+                    }
+                }
+            }
         }
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) pr[A + j][k] = roundtrip(p[j][k], static_cast<const T *>(nullptr));
+            for (int k = 0; k < 3; ++k) pr[s + j][k] = roundtrip(p[j][k], static_cast<const T *>(nullptr));
     }
 }
 
-template <int NLMAX, int NNMAX, typename T>
+template <int NLMAX, int NI, bool TAIL, typename T>
 __global__ __launch_bounds__(GTHREADS) void k_flow_label(StepArgs a, FusedGeom g) {
-    // new flows' x and y components: [flow][component][row + 1][column + 1],
+    using SL = Slots<NLMAX, NI, TAIL>;
+    constexpr int NS = SL::N;
+    // new flows' x and y components: [slot][component][row + 1][column + 1],
     // row 0 the halo row y0 - 1 and column 0 the halo column x0 - 1
-    __shared__ float lq[NNMAX][2][GY + 1][GX + 1];
+    __shared__ float lq[NS][2][GY + 1][GX + 1];
     const int row = threadIdx.x / GX;      // GY: halo row, GY + 1: halo column
     const int col = threadIdx.x % GX;
 
@@ -133,26 +182,26 @@ __global__ __launch_bounds__(GTHREADS) void k_flow_label(StepArgs a, FusedGeom g
 
     // rounded q_z of the new flows one plane below (the z neighbour of the
     // divergence); a chunk that starts above plane 0 recomputes that plane
-    float pzb[NNMAX];
+    float pzb[NS];
 #pragma unroll
-    for (int A = 0; A < NNMAX; ++A) pzb[A] = 0.f;
+    for (int s = 0; s < NS; ++s) pzb[s] = 0.f;
     if (own && zs > 0) {
-        float e0[NLMAX], pr[NNMAX][3];
-        flow_point<NLMAX, NNMAX, T>(a, b, xa, ya, zs - 1, false, e0, pr);
+        float e0[NLMAX], pr[NS][3];
+        flow_point<NLMAX, NI, TAIL, T>(a, b, xa, ya, zs - 1, false, e0, pr);
 #pragma unroll
-        for (int A = 0; A < NNMAX; ++A) pzb[A] = pr[A][2];
+        for (int s = 0; s < NS; ++s) pzb[s] = pr[s][2];
     }
 
     for (int z = zs; z < ze; ++z) {
-        float e0[NLMAX], pz[NNMAX], dl[NLMAX];
+        float e0[NLMAX], pz[NS], dl[NLMAX];
         if (va) {
-            float pr[NNMAX][3];
-            flow_point<NLMAX, NNMAX, T>(a, b, xa, ya, z, own, e0, pr);
+            float pr[NS][3];
+            flow_point<NLMAX, NI, TAIL, T>(a, b, xa, ya, z, own, e0, pr);
 #pragma unroll
-            for (int A = 0; A < NNMAX; ++A) {
-                lq[A][0][lr][lc] = pr[A][0];
-                lq[A][1][lr][lc] = pr[A][1];
-                pz[A] = pr[A][2];
+            for (int s = 0; s < NS; ++s) {
+                lq[s][0][lr][lc] = pr[s][0];
+                lq[s][1][lr][lc] = pr[s][1];
+                pz[s] = pr[s][2];
             }
         }
         if (own) {
@@ -162,22 +211,28 @@ __global__ __launch_bounds__(GTHREADS) void k_flow_label(StepArgs a, FusedGeom g
                 dl[L] = ldf(field<float>(a.D, b, a.nl, L < a.nl ? L : a.nl - 1, V), uv);
         }
         __syncthreads();
-        // label step of iteration k + 1 (label_body's expressions and order)
+        // label step of iteration k + 1 (label_body's expressions and order:
+        // the nodes in order, the internal ones first)
         if (own) {
             const unsigned uv = (unsigned)((z * a.ny + ya) * a.nx + xa);
             const bool bwd[3] = {xa > 0, ya > 0, z > 0};
             const bool fwd[3] = {xa < a.nx - 1, ya < a.ny - 1, z < a.nz - 1};
 #pragma unroll
-            for (int A = 0; A < NNMAX; ++A) {
-                const float q0[3] = {lq[A][0][lr][lc], lq[A][1][lr][lc], pz[A]};
-                const float qm[3] = {lq[A][0][lr][lc - 1], lq[A][1][lr - 1][lc], pzb[A]};
-                add_excess<NLMAX, false>(a, dl, A, div_from<3>(q0, qm, fwd, bwd));
+            for (int s = 0; s < NS; ++s) {
+                const float q0[3] = {lq[s][0][lr][lc], lq[s][1][lr][lc], pz[s]};
+                const float qm[3] = {lq[s][0][lr][lc - 1], lq[s][1][lr - 1][lc], pzb[s]};
+                const float dv = div_from<3>(q0, qm, fwd, bwd);
+                if (SL::tail(s)) {
+                    dl[s - NI] += dv;
+                } else {
+                    add_excess<NLMAX, false>(a, dl, s, dv);
+                }
             }
             entropic_step<NLMAX>(a, dl, e0);
 #pragma unroll
             for (int L = 0; L < NLMAX; L += 2) st_ell2<T>(a.ell_out, b, a.nl, L, V, uv, e0[L], e0[L + 1]);
 #pragma unroll
-            for (int A = 0; A < NNMAX; ++A) pzb[A] = pz[A];
+            for (int s = 0; s < NS; ++s) pzb[s] = pz[s];
         }
         __syncthreads();   // the plane's LDS flows are read
     }
@@ -191,13 +246,22 @@ bool flow_label_supported(int nd, int nl, int nn, bool identity) {
     return nd == 3 && !identity && nl <= 16 && nn <= 16;
 }
 
+// Builds with identity slots: at most 8 internal nodes (and 4 with more than
+// 12 leaves), an even count of them with 16-bit state.
+bool flow_label_tail_supported(int nl, int nn, int storage) {
+    const int ni = nn - nl;
+    if (ni < 0 || ni > 8 || (ni > 4 && nl > 12)) return false;
+    return storage == PF_FP32 || ni % 2 == 0;
+}
+
 // PF_KERNEL_AUTO takes this pass where it measured faster than the two-pass
 // kernels on MI355X: float32 state with more than 8 flows (per iteration:
-// DAGMF 256x512x512 9.63 against 10.86 ms, HMF 128x256x256 0.826 against
-// 0.841 ms; the 7-flow Ishikawa chain 0.637 against 0.625 ms).  With 16-bit
-// state the two-pass kernels stay ahead (DAGMF bf16 6.59 against 5.62 ms):
-// this pass is bound by its instruction latency at one block per compute
-// unit, the two-pass kernels by memory bandwidth.
+// DAGMF 256x512x512 9.30 against 10.9-11.5 ms, HMF 128x256x256 0.798 against
+// 0.843 ms; the 7-flow Ishikawa chain 0.64 against 0.62 ms).  With 16-bit
+// state the two-pass kernels stay ahead (DAGMF bf16 6.29 against 5.61 ms):
+// this pass issues about 1.3x the instructions of the two passes (halo
+// recomputation) at one block per compute unit, the two passes are bound by
+// memory bandwidth.
 bool flow_label_preferred(int nd, int nl, int nn, bool identity, int storage) {
     return storage == PF_FP32 && nn > 8 && flow_label_supported(nd, nl, nn, identity);
 }
@@ -206,21 +270,31 @@ bool flow_label_preferred(int nd, int nl, int nn, bool identity, int storage) {
 // planes (each chunk recomputes one flow plane below it).
 FusedGeom flow_label_geometry(const StepArgs &a) { return tile_geometry(a, GX, GY, 1024); }
 
-hipError_t launch_flow_label(const StepArgs &a, int storage, hipStream_t s) {
+hipError_t launch_flow_label(const StepArgs &a, int storage, bool tail, hipStream_t s) {
     if (!flow_label_supported(3, a.nl, a.nn, false) || a.nz < 1) return hipErrorInvalidValue;
     const FusedGeom g = flow_label_geometry(a);
     if (g.blocks <= 0 || g.blocks > 0x7fffffffL) return hipErrorInvalidValue;
-    auto go = [&]<int NL, int NN, typename T>() {
-        k_flow_label<NL, NN, T><<<(unsigned)g.blocks, GTHREADS, 0, s>>>(a, g);
+    const int ni = a.nn - a.nl;
+    tail = tail && flow_label_tail_supported(a.nl, a.nn, storage);
+    auto go = [&]<int NL, int NI, bool TL, typename T>() {
+        k_flow_label<NL, NI, TL, T><<<(unsigned)g.blocks, GTHREADS, 0, s>>>(a, g);
         return hipGetLastError();
     };
     auto by = [&]<typename T>() -> hipError_t {
-        if (a.nl <= 4 && a.nn <= 8) return go.template operator()<4, 8, T>();
-        if (a.nl <= 8 && a.nn <= 8) return go.template operator()<8, 8, T>();
-        if (a.nl <= 8 && a.nn <= 12) return go.template operator()<8, 12, T>();
-        if (a.nl <= 8 && a.nn <= 16) return go.template operator()<8, 16, T>();
-        if (a.nl <= 12 && a.nn <= 16) return go.template operator()<12, 16, T>();
-        return go.template operator()<16, 16, T>();
+        if (tail) {
+            if (ni <= 4 && a.nl <= 4) return go.template operator()<4, 4, true, T>();
+            if (ni <= 4 && a.nl <= 8) return go.template operator()<8, 4, true, T>();
+            if (ni <= 4 && a.nl <= 12) return go.template operator()<12, 4, true, T>();
+            if (ni <= 4) return go.template operator()<16, 4, true, T>();
+            if (a.nl <= 8) return go.template operator()<8, 8, true, T>();
+            return go.template operator()<12, 8, true, T>();
+        }
+        if (a.nl <= 4 && a.nn <= 8) return go.template operator()<4, 8, false, T>();
+        if (a.nl <= 8 && a.nn <= 8) return go.template operator()<8, 8, false, T>();
+        if (a.nl <= 8 && a.nn <= 12) return go.template operator()<8, 12, false, T>();
+        if (a.nl <= 8 && a.nn <= 16) return go.template operator()<8, 16, false, T>();
+        if (a.nl <= 12 && a.nn <= 16) return go.template operator()<12, 16, false, T>();
+        return go.template operator()<16, 16, false, T>();
     };
     if (storage == PF_BF16) return by.template operator()<bf16s>();
     if (storage == PF_FP16) return by.template operator()<f16s>();

@@ -123,8 +123,11 @@ FusedGeom fused2_geometry(const StepArgs &a);
 // one pass per iteration for 3-D label graphs: the flow step of iteration k,
 // then the label step of iteration k + 1 (state between passes: labels one
 // iteration ahead of the flows), ping-pong state
-hipError_t launch_flow_label(const StepArgs &a, int storage, hipStream_t s);
+// `tail`: the last nl of the nn nodes are the end-labels in order, so their
+// path-weight rows are unit vectors (the pass then skips their products)
+hipError_t launch_flow_label(const StepArgs &a, int storage, bool tail, hipStream_t s);
 bool flow_label_supported(int nd, int nl, int nn, bool identity);
+bool flow_label_tail_supported(int nl, int nn, int storage);
 bool flow_label_preferred(int nd, int nl, int nn, bool identity, int storage);
 // PF_KERNEL_AUTO's choice of a one-pass-per-iteration kernel (either kind)
 inline bool any_fused_preferred(int nd, int nl, int nn, bool identity, int storage) {
