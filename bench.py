@@ -113,9 +113,15 @@ KERNEL_NAMES = {"fused2": "k_fused2", "fused": "k_fused", "two_pass": "k_label+k
 
 def _kernel_name(p, choice: str) -> str:
     """The kernel a choice launches per iteration: the fused kind on a 3-D
-    label graph is the flow-then-label pass."""
+    label graph is the flow-then-label pass; the LDS kind holds whole
+    problems for batches of 8 or more that fit (4096 voxels, 40960 floats),
+    tiles with ghost zones otherwise."""
     if choice == "fused" and p.kind != "potts" and p.ndim == 3:
         return "k_flow_label"
+    if choice == "lds":
+        B, V = p.shape[0], p.shape[1] * p.shape[2] * p.shape[3]
+        whole = B >= 8 and V <= 4096 and V * (p.n_leaf + 2 * p.n_node) <= 40960
+        return "k_lds2d" if whole else "k_tile2d"
     return KERNEL_NAMES[choice]
 
 
@@ -253,28 +259,43 @@ def adjoint_leg(dev, reps: int = 3) -> dict:
             "backward_hbm_frac": round(alg / HBM_PEAK_GBS, 4)}
 
 
-def potts2d_leg(dev, reps: int = 5) -> dict:
-    """The small 2-D Potts case (64 x 64, 3 labels, 200 iterations): whole
-    solves per second, median of `reps` (latency-bound, cache-resident)."""
+def potts2d_leg(dev, reps: int = 7) -> dict:
+    """The small 2-D Potts case (64 x 64, 3 labels, 200 iterations, final
+    energy included): whole solves per second, median of `reps`, with the
+    kernel AUTO takes (LDS tiles with ghost zones, eight iterations per
+    launch) against the forced two-pass kernels (two launches per
+    iteration), and the two solutions compared bit for bit."""
     import torch
 
     import paper_1501_07844_amd as pf
     from paper_1501_07844_amd import synth
     p = synth.potts2d_rects()
     D, S = _inputs(p, dev)
-    kw = dict(c=p.c, tau=p.tau, iters=p.iters, s_mode=p.s_mode, ndim=2, final_energy=True)
-    r = pf.solve_potts(D, S, **kw)
-    ts = []
-    for _ in range(reps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = pf.solve_potts(D, S, workspace=r.workspace, **kw)
-        torch.cuda.synchronize()
-        ts.append(time.perf_counter() - t0)
-    t = sorted(ts)[len(ts) // 2]
-    return {"workload": "potts2d_rects 64x64, 3 labels, 200 iterations, fp32",
-            "ms_per_solve": round(1e3 * t, 3), "iterations_per_s": round(p.iters / t, 1),
-            "energy": r.energy, "gap": r.gap}
+    out = {"workload": "potts2d_rects 64x64, 3 labels, 200 iterations, fp32"}
+    sols = {}
+    for name, kernel in (("auto", "auto"), ("two_pass", "two_pass")):
+        kw = dict(c=p.c, tau=p.tau, iters=p.iters, s_mode=p.s_mode, ndim=2, kernel=kernel,
+                  final_energy=True, return_q=True)
+        r = pf.solve_potts(D, S, **kw)
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = pf.solve_potts(D, S, workspace=r.workspace, **kw)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        t = sorted(ts)[len(ts) // 2]
+        sols[name] = r
+        out[name] = {"ms_per_solve": round(1e3 * t, 3), "iterations_per_s": round(p.iters / t, 1)}
+    choice = _kernel_choice(pf, p, "fp32", "auto")
+    out["auto"]["kernel"] = _kernel_name(p, choice)
+    out["ms_per_solve"] = out["auto"]["ms_per_solve"]
+    out["iterations_per_s"] = out["auto"]["iterations_per_s"]
+    out["speedup_vs_two_pass"] = round(out["two_pass"]["ms_per_solve"] / out["auto"]["ms_per_solve"], 3)
+    a, b = sols["auto"], sols["two_pass"]
+    out["same_u_q_bitwise"] = bool(torch.equal(a.u, b.u) and torch.equal(a.q, b.q))
+    out["energy"], out["gap"] = a.energy, a.gap
+    return out
 
 
 def potts2d_batch_leg(dev, batch: int = 256, reps: int = 5) -> dict:

@@ -69,8 +69,11 @@ typedef enum {
 
 typedef enum {
     PF_KERNEL_AUTO = 0,      /* the faster variant as measured on MI355X: LDS for
-                                batches of 8 or more 2-D problems that it supports;
-                                for 3-D Potts FUSED2 up to 8 labels (every storage
+                                batches of 8 or more 2-D problems that fit whole,
+                                and for other 2-D problems of at most 8 leaves and
+                                8 flows up to 2^21 voxel-fields (voxels x problems
+                                x (n_leaf + n_node)); for 3-D Potts FUSED2 up to 8
+                                labels (every storage
                                 type), beyond that FUSED with fp32 state; FUSED for
                                 3-D label graphs (DAGMF, HMF, Ishikawa chain) of 9 to
                                 16 flows and at most 16 leaves with fp32 state;
@@ -87,11 +90,16 @@ typedef enum {
                                 PF_EUNSUPPORTED otherwise), state ping-ponged; an
                                 iteration that ends on a gap check, or the last of an
                                 odd count, runs the one-iteration pass */
-    PF_KERNEL_LDS = 4        /* 2-D problems of at most 4096 voxels, 8 leaves and 16
-                                flows whose float32 state, n_leaf + 2 n_node floats
-                                per voxel, fits in 160 KB of LDS: one launch runs
-                                every iteration up to the next gap check, one block
-                                per problem (PF_EUNSUPPORTED otherwise) */
+    PF_KERNEL_LDS = 4        /* 2-D problems of at most 8 leaves and 16 flows
+                                (PF_EUNSUPPORTED otherwise), iterations in LDS: for
+                                batches of 8 or more problems of at most 4096 voxels
+                                whose float32 state, n_leaf + 2 n_node floats per
+                                voxel, fits in 160 KB, one block per problem and one
+                                launch for every iteration up to the next gap check
+                                (state in place); otherwise tiles with ghost zones 8
+                                voxels wide, one block per tile and up to 8
+                                iterations per launch (state ping-ponged); the same
+                                result as PF_KERNEL_TWO_PASS bit for bit */
 } pf_kernel;
 
 typedef struct {
@@ -120,7 +128,8 @@ typedef struct {
     int32_t timing_stride;   /* > 0: time the launch starting every timing_stride-th
                                 iteration with HIP events (one launch covers two
                                 iterations with PF_KERNEL_FUSED2; with PF_KERNEL_LDS
-                                every launch is timed) */
+                                the launches of every chunk of iterations up to the
+                                next gap check are timed as one) */
     void *workspace;         /* device, 256-byte aligned, caller-owned */
     size_t workspace_bytes;
     /* Differentiable solves (float32 state only).  With tape != NULL the
@@ -199,8 +208,8 @@ int solve_hmf(const pf_grid *grid, const pf_graph *graph, const float *D, const 
  * L_i driven by U_i = sum_{j>=i} u_j.  D: device float[B][N+1][Z][Y][X];
  * S per s_mode with n_node = N.  Supports PF_KERNEL_TWO_PASS, PF_KERNEL_LDS,
  * PF_KERNEL_FUSED on 3-D grids, and AUTO (the rule of pf_auto_kernel with
- * identity = 0: LDS for batches of 8 or more 2-D problems that fit, FUSED on
- * 3-D grids, else two-pass). */
+ * identity = 0: LDS for small 2-D problems, FUSED on 3-D grids, else
+ * two-pass). */
 int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
                    int32_t s_mode, const pf_params *params, pf_result *result, void *stream);
 

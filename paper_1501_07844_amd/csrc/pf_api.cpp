@@ -326,15 +326,21 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream, bool stat
                     P->kernel == PF_KERNEL_LDS))
         return fail(PF_EUNSUPPORTED, "a recorded solve uses the two-pass kernels");
     const long V = (long)p.g.nx * p.g.ny * p.g.nz;
-    const bool want_lds = !P->tape && (P->kernel == PF_KERNEL_LDS ||
+    // PF_KERNEL_LDS: whole problems per block for batches that fill the GPU
+    // (and fit), tiles with ghost zones otherwise
+    const bool lds_kind = !P->tape && (P->kernel == PF_KERNEL_LDS ||
                           (P->kernel == PF_KERNEL_AUTO &&
-                           lds_preferred(p.g.ndim, p.nl, p.nn, V, p.g.batch)));
-    if (want_lds && !lds_supported(p.g.ndim, p.nl, p.nn, V))
-        return fail(PF_EUNSUPPORTED, "the state of one problem does not fit in LDS");
-    const bool want_fused2 = !P->tape && !want_lds && (P->kernel == PF_KERNEL_FUSED2 ||
+                           (lds_preferred(p.g.ndim, p.nl, p.nn, V, p.g.batch) ||
+                            tile_preferred(p.g.ndim, p.nl, p.nn, V, p.g.batch))));
+    const bool want_lds = lds_kind && lds_preferred(p.g.ndim, p.nl, p.nn, V, p.g.batch);
+    const bool want_tile = lds_kind && !want_lds;
+    if (want_tile && !tile_supported(p.g.ndim, p.nl, p.nn))
+        return fail(PF_EUNSUPPORTED, "LDS-resident iterations serve 2-D problems of up to 8 labels "
+                                     "and 16 flows");
+    const bool want_fused2 = !P->tape && !lds_kind && (P->kernel == PF_KERNEL_FUSED2 ||
                              (P->kernel == PF_KERNEL_AUTO &&
                               fused2_preferred(p.g.ndim, p.nl, p.nn, p.ident, P->storage)));
-    const bool want_fused = want_fused2 || (!P->tape && !want_lds && (P->kernel == PF_KERNEL_FUSED ||
+    const bool want_fused = want_fused2 || (!P->tape && !lds_kind && (P->kernel == PF_KERNEL_FUSED ||
                             (P->kernel == PF_KERNEL_AUTO &&
                              any_fused_preferred(p.g.ndim, p.nl, p.nn, p.ident, P->storage))));
     if (P->kernel == PF_KERNEL_FUSED && !fused_supported(p.g.ndim, p.nl, p.nn, p.ident))
@@ -346,7 +352,7 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream, bool stat
     // pass); the label-then-flow fused kernel serves Potts and 2-D graphs
     const bool want_fl = want_fused && !want_fused2 &&
                          flow_label_supported(p.g.ndim, p.nl, p.nn, p.ident);
-    const Layout lay = make_layout(p.g, p.nl, p.nn, P->storage, want_fused);
+    const Layout lay = make_layout(p.g, p.nl, p.nn, P->storage, want_fused || want_tile);
     if (static_ws && lay.total > (size_t)PF_STATIC_SCRATCH_BYTES)
         return fail(PF_ENOMEM, "the problem needs %zu bytes of device scratch, more than the %zu "
                                "bytes of the static scratch", lay.total, (size_t)PF_STATIC_SCRATCH_BYTES);
@@ -453,7 +459,7 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream, bool stat
                           !(P->gap_every > 0 && (it + 1) % P->gap_every == 0);
         // the LDS kernel and the flow-then-label passes run every iteration up
         // to the next gap check
-        const int step = (want_lds || want_fl)
+        const int step = (want_lds || want_tile || want_fl)
                              ? (P->gap_every > 0 ? std::min(P->iters - it,
                                                             P->gap_every - it % P->gap_every)
                                                  : P->iters - it)
@@ -466,7 +472,8 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream, bool stat
                                    reinterpret_cast<float *>(slot + tg.ell_bytes), n_q, stream)) != hipSuccess)
                 return hip_fail(e, "checkpoint");
         }
-        const bool timed = !want_fl && P->timing_stride > 0 && (want_lds || it % P->timing_stride == 0);
+        const bool timed = !want_fl && P->timing_stride > 0 &&
+                           (want_lds || want_tile || it % P->timing_stride == 0);
         if (timed) {
             hipEvent_t e0, e1;
             if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -478,6 +485,20 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream, bool stat
         if (want_lds) {
             if ((e = launch_lds(a, ident, P->storage, step, stream)) != hipSuccess)
                 return hip_fail(e, "LDS-resident iterations");
+        } else if (want_tile) {
+            // launches of up to k iterations each, ping-pong
+            const int kmax = tile_geometry(a.nx, a.ny, a.B, a.nn).k;
+            for (int j = 0; j < step; j += kmax) {
+                a.ell_in = ell[cur];
+                a.q_in = q[cur];
+                a.ell_out = ell[1 - cur];
+                a.q_out = q[1 - cur];
+                if ((e = launch_tile(a, ident, P->storage, std::min(kmax, step - j), stream)) != hipSuccess)
+                    return hip_fail(e, "LDS tile iterations");
+                cur = 1 - cur;
+            }
+            a.ell_in = a.ell_out = ell[cur];
+            a.q_in = a.q_out = q[cur];
         } else if (want_fl) {
             // label step of iteration it + 1 in place, `step - 1` passes each
             // taking the flows and the labels one iteration further (ping-pong),
@@ -783,9 +804,13 @@ size_t pf_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t n_node,
     if (n_leaf < 1 || n_leaf > PF_MAX_LEAVES || n_node < 1 || n_node > PF_MAX_NODES) return 0;
     if (params->storage < PF_FP32 || params->storage > PF_FP16) return 0;
     // the same sizes serve the identity (Potts) and weighted families
+    const long V = (long)grid->nx * grid->ny * grid->nz;
     const bool fused = params->kernel == PF_KERNEL_FUSED || params->kernel == PF_KERNEL_FUSED2 ||
+                       (params->kernel == PF_KERNEL_LDS &&
+                        !lds_preferred(grid->ndim, n_leaf, n_node, V, grid->batch)) ||
                        (params->kernel == PF_KERNEL_AUTO &&
-                        (any_fused_preferred(grid->ndim, n_leaf, n_node, true, params->storage) ||
+                        (tile_preferred(grid->ndim, n_leaf, n_node, V, grid->batch) ||
+                         any_fused_preferred(grid->ndim, n_leaf, n_node, true, params->storage) ||
                          any_fused_preferred(grid->ndim, n_leaf, n_node, false, params->storage) ||
                          fused2_preferred(grid->ndim, n_leaf, n_node, true, params->storage)));
     return make_layout(*grid, n_leaf, n_node, params->storage, fused).total;
@@ -798,7 +823,9 @@ int32_t pf_auto_kernel(const pf_grid *grid, int32_t n_leaf, int32_t n_node, int3
     if (storage < PF_FP32 || storage > PF_FP16) return -1;
     const bool id = identity != 0;
     if (id && n_node != n_leaf) return -1;
-    if (lds_preferred(grid->ndim, n_leaf, n_node, (long)grid->nx * grid->ny * grid->nz, grid->batch))
+    const long V = (long)grid->nx * grid->ny * grid->nz;
+    if (lds_preferred(grid->ndim, n_leaf, n_node, V, grid->batch) ||
+        tile_preferred(grid->ndim, n_leaf, n_node, V, grid->batch))
         return PF_KERNEL_LDS;
     if (fused2_preferred(grid->ndim, n_leaf, n_node, id, storage)) return PF_KERNEL_FUSED2;
     if (any_fused_preferred(grid->ndim, n_leaf, n_node, id, storage)) return PF_KERNEL_FUSED;
@@ -1076,10 +1103,15 @@ int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const 
     if ((st = check_inputs_common(p, D, S, s_mode)) != PF_OK) return st;
     pf_params P2 = *params;
     const long V = (long)p.g.nx * p.g.ny * p.g.nz;
-    if (P2.kernel == PF_KERNEL_AUTO)
-        P2.kernel = lds_preferred(p.g.ndim, p.nl, p.nn, V, p.g.batch)            ? PF_KERNEL_LDS
-                    : any_fused_preferred(p.g.ndim, p.nl, p.nn, false, P2.storage) ? PF_KERNEL_FUSED
-                                                                               : PF_KERNEL_TWO_PASS;
+    if (P2.kernel == PF_KERNEL_AUTO) {
+        if (lds_preferred(p.g.ndim, p.nl, p.nn, V, p.g.batch) ||
+            tile_preferred(p.g.ndim, p.nl, p.nn, V, p.g.batch))
+            P2.kernel = PF_KERNEL_LDS;
+        else if (any_fused_preferred(p.g.ndim, p.nl, p.nn, false, P2.storage))
+            P2.kernel = PF_KERNEL_FUSED;
+        else
+            P2.kernel = PF_KERNEL_TWO_PASS;
+    }
     return run(p, &P2, result, static_cast<hipStream_t>(stream));
 }
 

@@ -111,6 +111,21 @@ constexpr int kLdsFloats = 40 * 1024;   // 160 KB of LDS per block
 bool lds_supported(int nd, int nl, int nn, long V);
 bool lds_preferred(int nd, int nl, int nn, long V, int batch);
 hipError_t launch_lds(const StepArgs &a, bool ident, int storage, int iters, hipStream_t s);
+// 2-D tiles with ghost zones in LDS: up to TileGeom::k iterations per launch,
+// one block per owned tile and problem, ping-pong state
+struct TileGeom {
+    int32_t ox, oy;          // owned tile
+    int32_t k;               // ghost zone width = iterations per launch at most
+    int32_t rw, rh;          // region extents (owned + ghosts, clipped to the image)
+    int32_t tiles_x, tiles_y;
+};
+// one voxel of the region per thread: up to 32 x 32, 24 x 24 for builds of
+// more than 8 flows (their registers)
+constexpr int tile_threads(int nn_build) { return nn_build > 8 ? 576 : 1024; }
+bool tile_supported(int nd, int nl, int nn);
+bool tile_preferred(int nd, int nl, int nn, long V, int batch);
+TileGeom tile_geometry(int nx, int ny, int batch, int nn);
+hipError_t launch_tile(const StepArgs &a, bool ident, int storage, int iters, hipStream_t s);
 hipError_t launch_fused(const StepArgs &a, bool ident, int nd, int storage, hipStream_t s);
 bool fused_supported(int nd, int nl, int nn, bool identity);
 bool fused_preferred(int nd, int nl, int nn, bool identity, int storage);

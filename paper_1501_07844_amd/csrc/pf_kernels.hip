@@ -269,6 +269,132 @@ hipError_t lds_bucket(bool ident, int nl, int nn, F &f) {
     return f.template operator()<8, 16, false, T>();
 }
 
+// ------------------------------- LDS tiles with ghost zones (2-D) -------
+// A problem too small to fill the GPU (one 64 x 64 image) is bound by launch
+// latency in the two-pass kernels (two launches per iteration) and by one
+// compute unit's issue rate when it sits in one block (k_lds2d).  Here each
+// block owns a tile of g.ox x g.oy voxels and loads the tile plus a ghost
+// zone g.k voxels wide on each side (clipped at the image border) into LDS,
+// then performs up to g.k iterations there and stores its own tile.  The
+// label step at x reads flows at x - e_k and the flow step reads labels at
+// x + e_k, so each iteration leaves one more ghost layer stale on each side
+// and the owned tile is exact after g.k of them; the stale ghost values are
+// never read by an owned voxel, and reads past the loaded region are
+// clamped into it.  Blocks read the previous launch's state and write the
+// other buffer, so no launch reads what one of its blocks writes.  One voxel
+// per thread, the thread's data terms and capacities in registers, fields in
+// LDS at a stride of one float per thread; each voxel evaluates k_lds2d's
+// expressions (those of label_body / flow_body) with the same roundings, so
+// the result equals the two-pass kernels' bit for bit.
+template <int NLMAX, int NNMAX, bool IDENT, typename T>
+__global__ __launch_bounds__(tile_threads(NNMAX)) void k_tile2d(StepArgs a, TileGeom g, int iters) {
+    constexpr int R = tile_threads(NNMAX);
+    __shared__ float se[NLMAX * R];            // ell [nl][R]
+    __shared__ float sq[NNMAX * 2 * R];        // q [nn][2][R]
+    const T *Tn = nullptr;
+    const int tiles = g.tiles_x * g.tiles_y;
+    const int b = blockIdx.x / tiles;
+    const int tl = blockIdx.x - b * tiles;
+    const int ox0 = (tl % g.tiles_x) * g.ox, oy0 = (tl / g.tiles_x) * g.oy;
+    const int rx0 = max(0, ox0 - g.k), ry0 = max(0, oy0 - g.k);
+    const int rw = min(a.nx, ox0 + g.ox + g.k) - rx0;     // this block's region
+    const int rh = min(a.ny, oy0 + g.oy + g.k) - ry0;
+    const int lx = (int)threadIdx.x % g.rw, ly = (int)threadIdx.x / g.rw;
+    const bool act = ly < g.rh && lx < rw && ly < rh;
+    const int x = rx0 + (act ? lx : 0), y = ry0 + (act ? ly : 0);
+    const int r = ly * g.rw + lx;
+    const size_t Vs = (size_t)a.V;
+    const unsigned v = (unsigned)(y * a.nx + x);
+    // LDS neighbours, clamped into the region
+    const int rxm = lx > 0 ? r - 1 : r, rym = ly > 0 ? r - g.rw : r;
+    const int rxp = lx < rw - 1 ? r + 1 : r, ryp = ly < rh - 1 ? r + g.rw : r;
+    const bool bwd[3] = {x > 0, y > 0, false};
+    const bool fwd[3] = {x < a.nx - 1, y < a.ny - 1, false};
+    float dr[NLMAX], sv[NNMAX];
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L) dr[L] = ldf(field<float>(a.D, b, a.nl, L < a.nl ? L : a.nl - 1, Vs), v);
+#pragma unroll
+    for (int A = 0; A < NNMAX; ++A) sv[A] = smooth(a, b, A < a.nn ? A : a.nn - 1, (int)v);
+    if (act) {
+#pragma unroll
+        for (int L = 0; L < NLMAX; ++L)
+            if (L < a.nl) se[L * R + r] = ld_ell<T>(a.ell_in, b, a.nl, L, Vs, v);
+#pragma unroll
+        for (int A = 0; A < NNMAX; ++A)
+            if (A < a.nn)
+#pragma unroll
+                for (int k = 0; k < 2; ++k) sq[(A * 2 + k) * R + r] = ld_q<T, 2>(a.q_in, b, a.nn, A, k, Vs, v);
+    }
+    __syncthreads();
+    for (int it = 0; it < iters; ++it) {
+        if (act) {
+            // label step (label_body)
+            float d[NLMAX], e[NLMAX], q0[NNMAX][3], qm[NNMAX][3];
+#pragma unroll
+            for (int L = 0; L < NLMAX; ++L) {
+                d[L] = dr[L];
+                e[L] = se[(L < a.nl ? L : a.nl - 1) * R + r];
+            }
+#pragma unroll
+            for (int A = 0; A < NNMAX; ++A) {
+                const int Ac = A < a.nn ? A : a.nn - 1;
+                q0[A][0] = sq[(Ac * 2) * R + r];
+                q0[A][1] = sq[(Ac * 2 + 1) * R + r];
+                qm[A][0] = sq[(Ac * 2) * R + rxm];
+                qm[A][1] = sq[(Ac * 2 + 1) * R + rym];
+            }
+#pragma unroll
+            for (int A = 0; A < NNMAX; ++A)
+                add_excess<NLMAX, IDENT>(a, d, A, div_from<2>(q0[A], qm[A], fwd, bwd));
+            entropic_step<NLMAX>(a, d, e);
+#pragma unroll
+            for (int L = 0; L < NLMAX; ++L)
+                if (L < a.nl) se[L * R + r] = roundtrip(e[L], Tn);
+        }
+        __syncthreads();
+        if (act) {
+            // flow step (flow_body)
+            const bool h[3] = {fwd[0], fwd[1], false};
+            const int nb[2] = {rxp, ryp};
+            float gu[NLMAX][2];
+#pragma unroll
+            for (int L = 0; L < NLMAX; ++L) {
+                const int Lc = L < a.nl ? L : a.nl - 1;
+                const float u0 = __expf(se[Lc * R + r]);
+#pragma unroll
+                for (int k = 0; k < 2; ++k) gu[L][k] = h[k] ? __expf(se[Lc * R + nb[k]]) - u0 : 0.f;
+            }
+#pragma unroll
+            for (int A = 0; A < NNMAX; ++A) {
+                if (A < a.nn) {
+                    const float qv[2] = {sq[(A * 2) * R + r], sq[(A * 2 + 1) * R + r]};
+                    float G[3], p[2];
+                    grad_U<2, NLMAX, IDENT>(a, A, gu, G);
+                    flow_project<2>(a, qv, G, h, sv[A], p);
+                    sq[(A * 2) * R + r] = roundtrip(p[0], Tn);
+                    sq[(A * 2 + 1) * R + r] = roundtrip(p[1], Tn);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // store the owned tile
+    if (act && x >= ox0 && x < ox0 + g.ox && y >= oy0 && y < oy0 + g.oy) {
+#pragma unroll
+        for (int L = 0; L < NLMAX; L += 2)
+            if (L < a.nl)
+                st_ell2<T>(a.ell_out, b, a.nl, L, Vs, v, se[L * R + r],
+                           L + 1 < a.nl ? se[(L + 1) * R + r] : 0.f);
+#pragma unroll
+        for (int A = 0; A < NNMAX; A += 2)
+            if (A < a.nn)
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+                    st_q2<T, 2>(a.q_out, b, a.nn, A, k, Vs, v, sq[(A * 2 + k) * R + r],
+                                A + 1 < a.nn ? sq[((A + 1) * 2 + k) * R + r] : 0.f);
+    }
+}
+
 // ------------------------------------------------- init / copy / export --
 
 template <typename T>
@@ -618,6 +744,53 @@ hipError_t launch_lds(const StepArgs &a, bool ident, int storage, int iters, hip
     return dispatch_type(storage, [&]<typename T>() {
         auto go = [&]<int NL, int NN, bool ID, typename U>() {
             k_lds2d<NL, NN, ID, U><<<(unsigned)a.B, kLdsThreads, 0, s>>>(a, iters);
+            return hipGetLastError();
+        };
+        return lds_bucket<T>(ident, a.nl, a.nn, go);
+    });
+}
+
+bool tile_supported(int nd, int nl, int nn) { return nd == 2 && nl <= 8 && nn <= 16; }
+
+// Owned tiles of 16 x 16 voxels with ghost zones 8 wide (8 iterations per
+// launch, a region of up to 32 x 32 voxels per block) while the problems give
+// at least 64 tiles and the build has at most 8 flows; otherwise 8 x 8 owned
+// (regions of up to 24 x 24).
+TileGeom tile_geometry(int nx, int ny, int batch, int nn) {
+    TileGeom g{};
+    g.k = 8;
+    g.ox = g.oy = 16;
+    if (nn > 8 || (long)((nx + 15) / 16) * ((ny + 15) / 16) * batch < 64) g.ox = g.oy = 8;
+    g.rw = nx < g.ox + 2 * g.k ? nx : g.ox + 2 * g.k;
+    g.rh = ny < g.oy + 2 * g.k ? ny : g.oy + 2 * g.k;
+    g.tiles_x = (nx + g.ox - 1) / g.ox;
+    g.tiles_y = (ny + g.oy - 1) / g.oy;
+    return g;
+}
+
+// PF_KERNEL_AUTO takes the tiles for 2-D problems of at most 8 flows that
+// the whole-problem LDS solve does not take, up to 2^21 voxel-fields
+// (voxels x problems x (n_leaf + n_node)), where they measured faster than
+// the two-pass kernels on MI355X (per solve: 64 x 64 with 3 labels, 200
+// iterations, 0.49 against 1.26 ms, and 7 such problems 0.56 against 1.27;
+// 512 x 512 with 3 labels, 50 iterations, 0.40 against 0.69 ms; beyond:
+// 1024 x 1024 with 3 labels 1.25 against 1.34 ms, a 512 x 512 DAG of 5
+// leaves and 8 flows 1.23 against 0.95 ms).  The builds of more than 8
+// flows have 24 x 24 regions (9x the owned voxels) and stay with two-pass.
+bool tile_preferred(int nd, int nl, int nn, long V, int batch) {
+    return tile_supported(nd, nl, nn) && nn <= 8 && !lds_preferred(nd, nl, nn, V, batch) &&
+           V * batch * (nl + nn) <= (1L << 21);
+}
+
+hipError_t launch_tile(const StepArgs &a, bool ident, int storage, int iters, hipStream_t s) {
+    if (!tile_supported(2, a.nl, a.nn) || a.nz != 1 || iters < 1) return hipErrorInvalidValue;
+    const TileGeom g = tile_geometry(a.nx, a.ny, a.B, a.nn);
+    const long blocks = (long)g.tiles_x * g.tiles_y * a.B;
+    if (iters > g.k || blocks <= 0 || blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    return dispatch_type(storage, [&]<typename T>() {
+        auto go = [&]<int NL, int NN, bool ID, typename U>() {
+            if (g.rw * g.rh > tile_threads(NN)) return hipErrorInvalidValue;
+            k_tile2d<NL, NN, ID, U><<<(unsigned)blocks, tile_threads(NN), 0, s>>>(a, g, iters);
             return hipGetLastError();
         };
         return lds_bucket<T>(ident, a.nl, a.nn, go);

@@ -6,11 +6,14 @@ AddressSanitizer and UBSan, driven through the C ABI with host buffers.
    and dual bit for bit (fp32, bf16, fp16; odd label and flow counts, ragged
    tiles, several z chunks), and so does the two-iterations-per-pass kernel
    (odd iteration counts and gap checks mixing in one-iteration passes).
-2. Reverse: recorded forward + backward against autograd through the float64
+2. The full-flow Potts solver against its float64 reference implementation,
+   and solve_dagmf_static (the library's static scratch) against solve_dagmf
+   with a workspace, bit for bit, on two calls in a row.
+3. Reverse: recorded forward + backward against autograd through the float64
    reference implementation, and the fused reverse step bit for bit against
    the two-kernel one.
 
-Usage: python check.py path/to/libcpu.so [forward] [fused2] [lds] [flowlabel] [reverse]
+Usage: python check.py path/to/libcpu.so [forward] [fused2] [lds] [flowlabel] [fullflow] [static] [reverse]
 """
 import ctypes as C
 import os
@@ -23,10 +26,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 import paper_1501_07844_amd as pf                      # noqa: E402  (structs only)
 from paper_1501_07844_amd import synth                  # noqa: E402
+from oracle import fullflow_oracle as FF                # noqa: E402
 from oracle import pseudoflow_oracle as O               # noqa: E402
 
 lib = C.CDLL(sys.argv[1])
-for n in ("pf_tape_bytes", "pf_backward_workspace_bytes", "pf_workspace_bytes"):
+for n in ("pf_tape_bytes", "pf_backward_workspace_bytes", "pf_workspace_bytes",
+          "pf_fullflow_workspace_bytes"):
     getattr(lib, n).restype = C.c_size_t
 lib.pf_last_error.restype = C.c_char_p
 
@@ -40,7 +45,8 @@ def ptr(a):
     return C.c_void_p(a.ctypes.data)
 
 
-def solve(p, iters, kernel, storage, tape=None, every=0, want_ell=False, gap_every=0):
+def solve(p, iters, kernel, storage, tape=None, every=0, want_ell=False, gap_every=0, entry=None,
+          c=None, tau=None):
     B, Z, Y, X = p.shape
     nl, nn = p.n_leaf, p.n_node
     D = np.ascontiguousarray(p.D, np.float32)
@@ -48,13 +54,17 @@ def solve(p, iters, kernel, storage, tape=None, every=0, want_ell=False, gap_eve
     grid = pf._Grid(B, p.ndim, Z, Y, X)
     keep = []
     prm = pf._Params()
-    prm.iters, prm.c, prm.tau = iters, p.c, p.tau
+    prm.iters, prm.c, prm.tau = iters, p.c if c is None else c, p.tau if tau is None else tau
     prm.storage, prm.kernel, prm.final_energy = pf.STORAGE[storage], pf.KERNEL[kernel], 1
     prm.gap_every = gap_every
-    need = lib.pf_workspace_bytes(C.byref(grid), nl, nn, C.byref(prm))
-    wraw, wptr = aligned(need)
-    keep.append(wraw)
-    prm.workspace, prm.workspace_bytes = wptr, need
+    if entry == "fullflow":
+        need = lib.pf_fullflow_workspace_bytes(C.byref(grid), nl)
+    else:
+        need = lib.pf_workspace_bytes(C.byref(grid), nl, nn, C.byref(prm))
+    if entry != "static":
+        wraw, wptr = aligned(need)
+        keep.append(wraw)
+        prm.workspace, prm.workspace_bytes = wptr, need
     if tape is not None:
         prm.ckpt_every, prm.tape, prm.tape_bytes = every, tape[1], tape[2]
     u = np.zeros((B, nl, Z, Y, X), np.float32)
@@ -65,7 +75,13 @@ def solve(p, iters, kernel, storage, tape=None, every=0, want_ell=False, gap_eve
     if want_ell:
         r.ell = ell.ctypes.data
     mode = pf.S_MODE[p.s_mode]
-    if p.kind == "potts":
+    if entry == "fullflow":
+        st = lib.solve_potts_fullflow(C.byref(grid), nl, ptr(D), ptr(S), mode, C.byref(prm), C.byref(r), None)
+    elif entry == "static":
+        g = pf._graph_struct(p.graph, keep)
+        st = lib.solve_dagmf_static(C.byref(grid), C.byref(g), ptr(D), ptr(S), mode, C.byref(prm), C.byref(r),
+                                    None)
+    elif p.kind == "potts":
         st = lib.solve_potts(C.byref(grid), nl, ptr(D), ptr(S), mode, C.byref(prm), C.byref(r), None)
     elif p.kind == "ishikawa":
         st = lib.solve_ishikawa(C.byref(grid), nl, ptr(D), ptr(S), mode, C.byref(prm), C.byref(r), None)
@@ -103,15 +119,22 @@ def check_forward():
 def lds_cases():
     rng = np.random.default_rng(9)
     dag = synth.random_dag(rng, 3, 5)
+    wide = synth.random_dag(rng, 5, 7)
     return [
-        ("potts2d nl3 64x64", synth.potts2d_rects(), 9, 0),
-        ("potts2d nl5 B2 nodefield", synth.random_potts(7, (1, 37, 70), 2, 5, batch=2, s_mode="node_field"), 8, 3),
-        ("dag2d nl5 nn8 shared", synth.random_problem(8, (1, 26, 37), 2, dag, s_mode="shared_field"), 6, 4),
+        # tiles with ghost zones (fewer than 8 problems)
+        ("potts2d nl3 64x64", synth.potts2d_rects(), 19, 0),
+        ("potts2d nl5 B2 nodefield", synth.random_potts(7, (1, 37, 70), 2, 5, batch=2, s_mode="node_field"), 17, 3),
+        ("dag2d nl5 nn8 shared", synth.random_problem(8, (1, 26, 37), 2, dag, s_mode="shared_field"), 11, 4),
+        ("dag2d nl7 nn12 field", synth.random_problem(10, (1, 21, 30), 2, wide, s_mode="node_field"), 9, 0),
+        ("potts2d nl2 B3 thin", synth.random_potts(12, (1, 3, 41), 2, 2, batch=3), 10, 0),
+        # whole problems per block (8 or more)
+        ("potts2d nl3 B8 whole", synth.random_potts(13, (1, 20, 30), 2, 3, batch=8), 5, 2),
     ]
 
 
 def check_lds():
-    """The LDS-resident 2-D solve against the two-pass kernels."""
+    """The LDS-resident 2-D solves (tiles with ghost zones, whole problems)
+    against the two-pass kernels."""
     bad = 0
     for name, p, iters, gap_every in lds_cases():
         for storage in ("fp32", "bf16", "fp16"):
@@ -171,6 +194,47 @@ def check_flow_label():
             b = solve(p, iters, "fused", storage, gap_every=gap_every)
             same = all(np.array_equal(x, y) for x, y in zip(a[:2], b[:2])) and a[3:] == b[3:]
             print(f"forward {name:24s} {storage}: flow-label == two-pass bitwise: {same}", flush=True)
+            bad += not same
+    return bad
+
+
+def check_fullflow():
+    """The full-flow solver (float32) against its float64 reference: u and q
+    within 1e-4, energy and dual within 1e-4 relative."""
+    bad = 0
+    cases = [
+        ("potts2d nl3 rects", synth.potts2d_rects(), 0.3, 0.16, 30),
+        ("potts3d nl5 B2 field", synth.random_potts(21, (6, 9, 70), 3, 5, batch=2, s_mode="node_field",
+                                                    d_scale=3.0), 1.0, 0.1, 12),
+        ("potts3d nl12 shared", synth.random_potts(22, (5, 7, 40), 3, 12, s_mode="shared_field",
+                                                   d_scale=3.0), 1.0, 0.1, 8),
+    ]
+    for name, p, c, tau, iters in cases:
+        u, q, _, E, P = solve(p, iters, "auto", "fp32", entry="fullflow", c=c, tau=tau)
+        ref = FF.solve_potts_fullflow(p.D, p.S, p.s_mode, c, tau, iters, p.ndim)
+        du = np.abs(u - ref["u"].numpy()).max()
+        dq = np.abs(q - ref["q"].numpy()).max()
+        ok = du <= 1e-4 and dq <= 1e-4 and abs(E - ref["E"][-1]) <= 1e-4 * abs(ref["E"][-1]) \
+            and abs(P - ref["P"][-1]) <= 1e-4 * abs(ref["E"][-1])
+        print(f"fullflow {name:24s} max|du| {du:.1e} max|dq| {dq:.1e}: {'ok' if ok else 'BAD'}", flush=True)
+        bad += not ok
+    return bad
+
+
+def check_static():
+    """solve_dagmf_static against solve_dagmf with a workspace, bit for bit,
+    on two calls in a row (the second smaller)."""
+    bad = 0
+    rng = np.random.default_rng(23)
+    dag = synth.random_dag(rng, 3, 5)
+    for name, p in (("dag3d nl5 nn8 B2", synth.random_problem(24, (12, 9, 40), 3, dag, batch=2,
+                                                             s_mode="node_field")),
+                    ("dag2d nl5 nn8", synth.random_problem(25, (1, 11, 23), 2, dag, s_mode="shared_field"))):
+        for storage in ("fp32", "bf16"):
+            a = solve(p, 4, "auto", storage)
+            b = solve(p, 4, "auto", storage, entry="static")
+            same = all(np.array_equal(x, y) for x, y in zip(a[:2], b[:2])) and a[3:] == b[3:]
+            print(f"static {name:24s} {storage}: static scratch == workspace bitwise: {same}", flush=True)
             bad += not same
     return bad
 
@@ -271,6 +335,10 @@ if __name__ == "__main__":
         n_bad += check_lds()
     if not only or "flowlabel" in only:
         n_bad += check_flow_label()
+    if not only or "fullflow" in only:
+        n_bad += check_fullflow()
+    if not only or "static" in only:
+        n_bad += check_static()
     if not only or "reverse" in only:
         n_bad += check_reverse()
     print("ALL OK" if n_bad == 0 else f"{n_bad} FAILED")

@@ -26,6 +26,7 @@ def main(out):
     kd = k
     k = k[:k.index("// ----------------------------------------------------------- dispatch ----")]
     k += "\n}  // namespace\n" + cut(kd, "bool lds_supported(", "hipError_t launch_lds(")
+    k += cut(kd, "bool tile_supported(", "hipError_t launch_tile(")
     k += "\n}  // namespace pf\n"
     f = open(os.path.join(SRC, "pf_fused.hip")).read()
     fk = f[:f.index("template <int ND, typename T, typename F>\nhipError_t fused_bucket")]
@@ -38,14 +39,17 @@ def main(out):
     a = open(os.path.join(SRC, "pf_adjoint.hip")).read()
     ak = a[:a.index("unsigned sblocks(size_t n)")] + "\n}  // namespace\n"
     ak += cut(a, "bool adj_fused_supported(", "hipError_t launch_adj_flow(") + "\n}  // namespace pf\n"
+    ff = open(os.path.join(SRC, "pf_fullflow.hip")).read()
+    ffk = ff[:ff.index("template <typename F>\nhipError_t ff_dispatch")] + "\n}  // namespace\n"
+    ffk += cut(ff, "bool ff_supported(", "hipError_t launch_ff_init(") + "\n}  // namespace pf\n"
     # the constant address space cast has no host meaning
     d = open(os.path.join(SRC, "pf_device.h")).read().replace(
         "using cfloat = const __attribute__((address_space(4))) float;", "using cfloat = const float;")
     for name, text in (("kernels.inc", k), ("fused.inc", fk), ("flowlabel.inc", flk), ("adjoint.inc", ak),
-                       ("pf_device.h", d)):
+                       ("fullflow.inc", ffk), ("pf_device.h", d)):
         with open(os.path.join(out, name), "w") as fh:
             fh.write(text)
-    for name in ("pf_api.cpp", "pf_internal.h"):
+    for name in ("pf_api.cpp", "pf_internal.h", "pf_fullflow.h"):
         shutil.copy(os.path.join(SRC, name), os.path.join(out, name))
     shutil.copy(os.path.join(ROOT, "include", "pseudoflow.h"), os.path.join(out, "pseudoflow.h"))
 

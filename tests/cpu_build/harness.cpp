@@ -7,6 +7,7 @@
 #include "fused.inc"
 #include "flowlabel.inc"
 #include "adjoint.inc"
+#include "fullflow.inc"
 #include <cstdio>
 #include <cstdlib>
 #include <thread>
@@ -122,6 +123,19 @@ hipError_t launch_lds(const StepArgs &a, bool ident, int st, int iters, hipStrea
         return 0;
     });
 }
+hipError_t launch_tile(const StepArgs &a, bool ident, int st, int iters, hipStream_t) {
+    const TileGeom g = tile_geometry(a.nx, a.ny, a.B, a.nn);
+    if (!tile_supported(2, a.nl, a.nn) || a.nz != 1 || iters < 1 || iters > g.k) return 1;
+    const unsigned blocks = (unsigned)(g.tiles_x * g.tiles_y * a.B);
+    return disp(2, st, ident, a.nl, a.nn, [&]<int ND, int NL, int NN, bool ID, typename T>() {
+        if constexpr (NL <= 8 && NN <= 16) {
+            if (g.rw * g.rh > tile_threads(NN)) return 1;
+            run_grid(dim3(blocks), tile_threads(NN), true, [&] { k_tile2d<NL, NN, ID, T>(a, g, iters); });
+            return 0;
+        }
+        return 1;
+    });
+}
 hipError_t launch_fused(const StepArgs &a, bool ident, int nd, int st, hipStream_t) {
     const FusedGeom g = fused_geometry(a);
     auto f = [&]<int ND, int NL, int NN, bool ID, typename T>() {
@@ -143,20 +157,30 @@ hipError_t launch_fused2(const StepArgs &a, int st, hipStream_t) {
         return 0;
     });
 }
-hipError_t launch_flow_label(const StepArgs &a, int st, hipStream_t) {
+hipError_t launch_flow_label(const StepArgs &a, int st, bool tail, hipStream_t) {
     if (!flow_label_supported(3, a.nl, a.nn, false) || a.nz < 1) return 1;
     const FusedGeom g = flow_label_geometry(a);
-    auto go = [&]<int NL, int NN, typename T>() {
-        run_grid(dim3((unsigned)g.blocks), GTHREADS, true, [&] { k_flow_label<NL, NN, T>(a, g); });
+    const int ni = a.nn - a.nl;
+    tail = tail && flow_label_tail_supported(a.nl, a.nn, st);
+    auto go = [&]<int NL, int NI, bool TL, typename T>() {
+        run_grid(dim3((unsigned)g.blocks), GTHREADS, true, [&] { k_flow_label<NL, NI, TL, T>(a, g); });
         return 0;
     };
     auto by = [&]<typename T>() -> hipError_t {
-        if (a.nl <= 4 && a.nn <= 8) return go.template operator()<4, 8, T>();
-        if (a.nl <= 8 && a.nn <= 8) return go.template operator()<8, 8, T>();
-        if (a.nl <= 8 && a.nn <= 12) return go.template operator()<8, 12, T>();
-        if (a.nl <= 8 && a.nn <= 16) return go.template operator()<8, 16, T>();
-        if (a.nl <= 12 && a.nn <= 16) return go.template operator()<12, 16, T>();
-        return go.template operator()<16, 16, T>();
+        if (tail) {
+            if (ni <= 4 && a.nl <= 4) return go.template operator()<4, 4, true, T>();
+            if (ni <= 4 && a.nl <= 8) return go.template operator()<8, 4, true, T>();
+            if (ni <= 4 && a.nl <= 12) return go.template operator()<12, 4, true, T>();
+            if (ni <= 4) return go.template operator()<16, 4, true, T>();
+            if (a.nl <= 8) return go.template operator()<8, 8, true, T>();
+            return go.template operator()<12, 8, true, T>();
+        }
+        if (a.nl <= 4 && a.nn <= 8) return go.template operator()<4, 8, false, T>();
+        if (a.nl <= 8 && a.nn <= 8) return go.template operator()<8, 8, false, T>();
+        if (a.nl <= 8 && a.nn <= 12) return go.template operator()<8, 12, false, T>();
+        if (a.nl <= 8 && a.nn <= 16) return go.template operator()<8, 16, false, T>();
+        if (a.nl <= 12 && a.nn <= 16) return go.template operator()<12, 16, false, T>();
+        return go.template operator()<16, 16, false, T>();
     };
     return dtype(st, by);
 }
@@ -237,5 +261,44 @@ hipError_t launch_copy_f(const float *x, float *y, size_t n, hipStream_t) {
 hipError_t launch_sum_nodes(const float *sbar, int B, int nn, size_t V, float *out, hipStream_t) {
     run_grid(dim3(nn), 256, true, [&] { k_sum_nodes(sbar, B, nn, V, out); });
     return 0;
+}
+template <typename F> static hipError_t ffdisp(int nd, int n, F &&f) {
+    auto by = [&]<int ND>() -> hipError_t {
+        if (n <= 4) return f.template operator()<ND, 4>();
+        if (n <= 8) return f.template operator()<ND, 8>();
+        return f.template operator()<ND, 16>();
+    };
+    return nd == 2 ? by.template operator()<2>() : by.template operator()<3>();
+}
+hipError_t launch_ff_init(const StepArgs &a, const FFArgs &f, int nd, hipStream_t) {
+    return ffdisp(nd, a.nl, [&]<int ND, int NL>() {
+        run_grid(vgrid(a), kBlock, false, [&] { k_ff_init<ND, NL>(a, f); });
+        return 0;
+    });
+}
+hipError_t launch_ff_iteration(const StepArgs &a, const FFArgs &f, int nd, hipStream_t) {
+    return ffdisp(nd, a.nl, [&]<int ND, int NL>() {
+        run_grid(vgrid(a), kBlock, false, [&] { k_ff_flow<ND, NL>(a, f); });
+        run_grid(vgrid(a), kBlock, false, [&] { k_ff_rest<ND, NL>(a, f); });
+        return 0;
+    });
+}
+hipError_t launch_ff_energy(const StepArgs &a, const FFArgs &f, int nd, double *partials, double *results,
+                            hipStream_t) {
+    // 64 blocks, not kPartials, as launch_energy above
+    hipError_t e = ffdisp(nd, a.nl, [&]<int ND, int NL>() {
+        run_grid(dim3(64), kBlock, true, [&] { k_ff_energy<ND, NL>(a, f, partials); });
+        return 0;
+    });
+    for (int i = 64 * 4; i < kPartials * 4; ++i) partials[i] = (i % 4 == 3) ? -INFINITY : 0.0;
+    run_grid(dim3(1), kBlock, true, [&] { k_ff_reduce(partials, kPartials, results); });
+    return e;
+}
+hipError_t launch_ff_export(const StepArgs &a, const FFArgs &f, int nd, float *u, int32_t *labels, float *q,
+                            hipStream_t) {
+    return ffdisp(nd, a.nl, [&]<int ND, int NL>() {
+        run_grid(vgrid(a), kBlock, false, [&] { k_ff_export<ND, NL>(a, f, u, labels, q); });
+        return 0;
+    });
 }
 }  // namespace pf

@@ -15,6 +15,7 @@ extern thread_local std::barrier<> *emu_bar;
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
+#define __align__(n) __attribute__((aligned(n)))
 #define __shared__ static
 #define __syncthreads() emu_bar->arrive_and_wait()
 typedef int hipError_t;
@@ -31,9 +32,16 @@ static inline float __uint_as_float(uint32_t u) { float f; std::memcpy(&f, &u, 4
 static inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
 static inline int atomicOr(int32_t *p, int v) { int o = *p; *p |= v; return o; }
 static inline int min(int a, int b) { return a < b ? a : b; }
+static inline int max(int a, int b) { return a > b ? a : b; }
 extern "C" hipError_t hipMemcpyAsync(void *, const void *, size_t, int, hipStream_t);
 extern "C" hipError_t hipStreamSynchronize(hipStream_t);
 extern "C" const char *hipGetErrorString(hipError_t);
+typedef int hipDevice_t;
+static inline hipError_t hipGetDevice(int *d) { *d = 0; return 0; }
+static inline hipError_t hipStreamGetDevice(hipStream_t, hipDevice_t *d) { *d = 0; return 0; }
+// one device: the host array itself stands for its device copy
+#define HIP_SYMBOL(x) (&(x))
+template <typename T> static inline hipError_t hipGetSymbolAddress(void **p, T *sym) { *p = (void *)sym; return 0; }
 static inline hipError_t hipEventCreate(hipEvent_t *) { return 1; }
 static inline hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return 0; }
 static inline hipError_t hipEventDestroy(hipEvent_t) { return 0; }

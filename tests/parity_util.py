@@ -76,9 +76,7 @@ def supported_kernels(p):
         ks.append("fused")
     if p.kind == "potts" and p.ndim == 3 and p.n_leaf <= 8:
         ks.append("fused2")
-    V = p.shape[1] * p.shape[2] * p.shape[3]          # voxels per problem
-    if (p.ndim == 2 and p.n_leaf <= 8 and p.n_node <= 16 and V <= 4096
-            and V * (p.n_leaf + 2 * p.n_node) <= 40960):
+    if p.ndim == 2 and p.n_leaf <= 8 and p.n_node <= 16:
         ks.append("lds")
     return ks
 

@@ -76,15 +76,19 @@ def test_auto_kernel_choice():
     assert pf.auto_kernel((1, 16, 16, 16), 8, 8, 3, "bf16") == "fused2"
     assert pf.auto_kernel((1, 16, 16, 16), 8, 8, 3, "fp16") == "fused2"
     assert pf.auto_kernel((1, 16, 16, 16), 12, 12, 3, "bf16") == "two_pass"
-    assert pf.auto_kernel((1, 1, 64, 64), 8, 8, 2) == "two_pass"
+    # 2-D: whole problems in LDS for 8 or more that fit, tiles with ghost
+    # zones up to 2^21 voxel-fields and 8 flows, two-pass beyond
+    assert pf.auto_kernel((1, 1, 64, 64), 8, 8, 2) == "lds"                 # tiles
     assert pf.auto_kernel((8, 1, 64, 64), 3, 3, 2) == "lds"                 # 36864 of 40960 floats
-    assert pf.auto_kernel((1, 1, 64, 64), 3, 3, 2) == "two_pass"            # a single problem
-    assert pf.auto_kernel((7, 1, 64, 64), 3, 3, 2) == "two_pass"
+    assert pf.auto_kernel((1, 1, 64, 64), 3, 3, 2) == "lds"                 # a single problem: tiles
+    assert pf.auto_kernel((7, 1, 64, 64), 3, 3, 2) == "lds"
     assert pf.auto_kernel((16, 1, 40, 52), 5, 4, 2, identity=False) == "lds"
-    assert pf.auto_kernel((8, 1, 64, 64), 4, 4, 2) == "two_pass"            # 49152 floats > 40960
+    assert pf.auto_kernel((8, 1, 64, 64), 4, 4, 2) == "lds"                 # 49152 floats: tiles
     assert pf.auto_kernel((8, 1, 52, 64), 4, 4, 2) == "lds"                 # 39936 floats
-    assert pf.auto_kernel((8, 1, 64, 65), 3, 3, 2) == "two_pass"            # 4160 voxels > 4096
-    assert pf.auto_kernel((8, 1, 64, 64), 5, 5, 2) == "two_pass"            # 61440 floats > 40960
+    assert pf.auto_kernel((8, 1, 64, 65), 3, 3, 2) == "lds"                 # 4160 voxels: tiles
+    assert pf.auto_kernel((1, 1, 512, 682), 3, 3, 2) == "lds"               # just under 2^21 voxel-fields
+    assert pf.auto_kernel((1, 1, 512, 683), 3, 3, 2) == "two_pass"          # just above
+    assert pf.auto_kernel((64, 1, 64, 64), 5, 5, 2) == "two_pass"           # 2.6e6 voxel-fields
     assert pf.auto_kernel((8, 1, 40, 40), 9, 9, 2) == "two_pass"            # more than 8 labels
     assert pf.auto_kernel((1, 16, 16, 16), 8, 11, 3, identity=False) == "fused"
     assert pf.auto_kernel((1, 256, 512, 512), 12, 16, 3, identity=False) == "fused"
@@ -92,7 +96,8 @@ def test_auto_kernel_choice():
     assert pf.auto_kernel((1, 16, 16, 16), 16, 16, 3, "fp16", identity=False) == "two_pass"
     assert pf.auto_kernel((1, 16, 16, 16), 8, 7, 3, identity=False) == "two_pass"   # 7 flows
     assert pf.auto_kernel((1, 16, 16, 16), 16, 30, 3, identity=False) == "two_pass"  # 30 flows
-    assert pf.auto_kernel((1, 1, 64, 64), 8, 11, 2, identity=False) == "two_pass"   # 2-D
+    assert pf.auto_kernel((1, 1, 64, 64), 8, 11, 2, identity=False) == "two_pass"   # 2-D, 11 flows
+    assert pf.auto_kernel((1, 1, 64, 64), 5, 8, 2, identity=False) == "lds"         # 2-D, 8 flows
     lib = pf.library()
     assert lib.pf_auto_kernel(C.byref(_grid()), 4, 5, 1, 0) == -1          # Potts needs n_node == n_leaf
     assert lib.pf_auto_kernel(C.byref(_grid()), 4, 4, 1, 9) == -1          # storage
@@ -186,7 +191,7 @@ DEV = 1 << 20          # fake aligned pointers
     ("null_params", pf.PF_EINVAL), ("bad_kernel", pf.PF_EINVAL),
     ("fused2_2d", pf.PF_EUNSUPPORTED), ("fused2_9_labels", pf.PF_EUNSUPPORTED),
     ("fused2_recorded", pf.PF_EUNSUPPORTED), ("too_many_voxels", pf.PF_EUNSUPPORTED),
-    ("lds_3d", pf.PF_EUNSUPPORTED), ("lds_too_big", pf.PF_EUNSUPPORTED),
+    ("lds_3d", pf.PF_EUNSUPPORTED), ("lds_9_labels", pf.PF_EUNSUPPORTED),
     ("lds_recorded", pf.PF_EUNSUPPORTED),
 ])
 def test_potts_argument_errors(case, code):
@@ -233,8 +238,11 @@ def test_potts_argument_errors(case, code):
         p.kernel = 5
     elif case == "lds_3d":
         p.kernel = pf.KERNEL["lds"]
-    elif case == "lds_too_big":
-        g = _grid(1, 2, 1, 64, 80)            # 5120 voxels (at most 4096)
+    elif case == "lds_9_labels":
+        g = _grid(1, 2, 1, 9, 10)
+        n = 9
+        keep = (C.c_float * 9)(*([0.5] * 9))
+        S = C.addressof(keep)
         p.kernel = pf.KERNEL["lds"]
     elif case == "lds_recorded":
         g = _grid(1, 2, 1, 9, 10)

@@ -48,8 +48,12 @@ def test_kernel_choice_per_workload():
     assert bench._kernel_choice(pf, q, "fp32", "auto") == "two_pass"     # 7 flows
     assert bench._kernel_name(q, "fused") == "k_flow_label"
     assert bench._kernel_name(p, "fused") == "k_fused"
-    # a 2-D chain stays on the two-pass kernels (one problem: no LDS batch)
-    assert bench._kernel_choice(pf, synth.ishikawa_levels(), "fp32", "auto") == "two_pass"
+    # a small 2-D chain of one problem runs in LDS tiles with ghost zones
+    c2 = synth.ishikawa_levels()
+    assert bench._kernel_choice(pf, c2, "fp32", "auto") == "lds"
+    assert bench._kernel_name(c2, "lds") == "k_tile2d"
+    pb = synth.random_potts(1, (1, 20, 30), 2, 3, batch=8)
+    assert bench._kernel_name(pb, "lds") == "k_lds2d"
 
 
 @pytest.mark.parametrize("which", sorted(bench.TRAFFIC_FILES))

@@ -268,6 +268,15 @@ LDS_CASES = {
     "dag2d_nn15_B2": lambda: synth.random_problem(36, (1, 24, 40), 2,
                                                   synth.random_dag(np.random.default_rng(36), 7, 8),
                                                   batch=2, s_mode="node_scalar"),
+    # tiles with ghost zones: 16 x 16 owned tiles with ragged edges, 8 x 8
+    # owned tiles over a batch of 7, and a label graph over 16 x 16 tiles
+    "potts2d_nl3_150x200_tiles": lambda: synth.random_potts(37, (1, 150, 200), 2, 3,
+                                                            s_mode="node_field"),
+    "potts2d_nl8_B7_shared": lambda: synth.random_potts(38, (1, 45, 38), 2, 8, batch=7,
+                                                        s_mode="shared_field"),
+    "dag2d_nn8_B3_70x90": lambda: synth.random_problem(39, (1, 70, 90), 2,
+                                                       synth.random_dag(np.random.default_rng(39), 3, 5),
+                                                       batch=3, s_mode="node_field"),
 }
 
 
@@ -368,7 +377,7 @@ def test_unsupported_kernels_are_rejected():
     """Every documented PF_EUNSUPPORTED case returns that code through the
     C ABI (and leaves nothing half-done): two iterations per pass outside 3-D
     Potts up to 8 labels, the fused pass for the 2-D Ishikawa chain or beyond
-    16 flows, the LDS-resident solve for 3-D or oversized 2-D problems."""
+    16 flows, the LDS-resident solve for 3-D problems or more than 8 labels."""
     deep = synth.random_problem(201, (3, 5, 6), 3, synth.random_dag(np.random.default_rng(7), 15, 16,
                                                                     max_parents=2))
     cases = ((synth.random_potts(1, (1, 9, 11), 2, 4), "fused2", "2-D"),
@@ -378,7 +387,6 @@ def test_unsupported_kernels_are_rejected():
              (synth.ishikawa_levels(shape=(1, 9, 10), iters=2), "fused2", "Ishikawa chain"),
              (deep, "fused", "30 flows"),
              (synth.random_potts(3, (3, 5, 7), 3, 3), "lds", "3-D"),
-             (synth.random_potts(4, (1, 70, 70), 2, 3), "lds", "4900 voxels"),
              (synth.random_potts(5, (1, 30, 30), 2, 12), "lds", "12 labels"))
     for p, kernel, why in cases:
         assert kernel not in supported_kernels(p), why
