@@ -73,11 +73,13 @@ typedef enum {
                                 and for other 2-D problems of at most 8 leaves and
                                 8 flows up to 2^21 voxel-fields (voxels x problems
                                 x (n_leaf + n_node)); for 3-D Potts FUSED2 up to 8
-                                labels (every storage
-                                type), beyond that FUSED with fp32 state; FUSED for
-                                3-D label graphs (DAGMF, HMF, Ishikawa chain) of 9 to
-                                16 flows and at most 16 leaves with fp32 state;
-                                two-pass otherwise */
+                                labels (every storage type), beyond that FUSED with
+                                fp32 state; FUSED for 3-D label graphs (DAGMF, HMF,
+                                Ishikawa chain) of 9 to 16 flows and at most 16
+                                leaves with fp32 state, and in every storage type
+                                for 3-D graphs whose end-labels are the last nodes,
+                                under 4 internal nodes with 4, 8, 12 or 16 leaves
+                                or under 8 with 8 or 12; two-pass otherwise */
     PF_KERNEL_TWO_PASS = 1,  /* label pass then flow pass, state updated in place */
     PF_KERNEL_FUSED = 2,     /* one pass per iteration, state ping-ponged (at most 16
                                 leaves and 16 flows; 3-D label graphs run the flow
@@ -170,8 +172,9 @@ size_t pf_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t n_node,
 
 /* The kernel PF_KERNEL_AUTO runs for an unrecorded solve of this problem:
  * identity != 0 for the Potts model, 0 for a label graph (DAGMF, HMF, and the
- * Ishikawa chain, whose AUTO follows the same rule); storage is a pf_storage.
- * Host only, no device work.  Returns PF_KERNEL_TWO_PASS, PF_KERNEL_FUSED,
+ * Ishikawa chain, whose AUTO follows the same rule; a graph is taken to
+ * number its end-labels last, as every graph whose leaves have the highest
+ * node ids does); storage is a pf_storage.  Host only, no device work.  Returns PF_KERNEL_TWO_PASS, PF_KERNEL_FUSED,
  * PF_KERNEL_FUSED2 or PF_KERNEL_LDS, or -1 for arguments no solver accepts. */
 int32_t pf_auto_kernel(const pf_grid *grid, int32_t n_leaf, int32_t n_node, int32_t identity,
                        int32_t storage);

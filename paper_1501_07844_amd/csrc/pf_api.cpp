@@ -342,7 +342,7 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream, bool stat
                               fused2_preferred(p.g.ndim, p.nl, p.nn, p.ident, P->storage)));
     const bool want_fused = want_fused2 || (!P->tape && !lds_kind && (P->kernel == PF_KERNEL_FUSED ||
                             (P->kernel == PF_KERNEL_AUTO &&
-                             any_fused_preferred(p.g.ndim, p.nl, p.nn, p.ident, P->storage))));
+                             any_fused_preferred(p.g.ndim, p.nl, p.nn, p.ident, P->storage, p.tail))));
     if (P->kernel == PF_KERNEL_FUSED && !fused_supported(p.g.ndim, p.nl, p.nn, p.ident))
         return fail(PF_EUNSUPPORTED, "fused kernel unavailable for this problem");
     if (want_fused2 && !fused2_supported(p.g.ndim, p.nl, p.nn, p.ident))
@@ -810,8 +810,8 @@ size_t pf_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t n_node,
                         !lds_preferred(grid->ndim, n_leaf, n_node, V, grid->batch)) ||
                        (params->kernel == PF_KERNEL_AUTO &&
                         (tile_preferred(grid->ndim, n_leaf, n_node, V, grid->batch) ||
-                         any_fused_preferred(grid->ndim, n_leaf, n_node, true, params->storage) ||
-                         any_fused_preferred(grid->ndim, n_leaf, n_node, false, params->storage) ||
+                         any_fused_preferred(grid->ndim, n_leaf, n_node, true, params->storage, true) ||
+                         any_fused_preferred(grid->ndim, n_leaf, n_node, false, params->storage, true) ||
                          fused2_preferred(grid->ndim, n_leaf, n_node, true, params->storage)));
     return make_layout(*grid, n_leaf, n_node, params->storage, fused).total;
 }
@@ -828,7 +828,7 @@ int32_t pf_auto_kernel(const pf_grid *grid, int32_t n_leaf, int32_t n_node, int3
         tile_preferred(grid->ndim, n_leaf, n_node, V, grid->batch))
         return PF_KERNEL_LDS;
     if (fused2_preferred(grid->ndim, n_leaf, n_node, id, storage)) return PF_KERNEL_FUSED2;
-    if (any_fused_preferred(grid->ndim, n_leaf, n_node, id, storage)) return PF_KERNEL_FUSED;
+    if (any_fused_preferred(grid->ndim, n_leaf, n_node, id, storage, true)) return PF_KERNEL_FUSED;
     return PF_KERNEL_TWO_PASS;
 }
 
@@ -1107,7 +1107,7 @@ int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const 
         if (lds_preferred(p.g.ndim, p.nl, p.nn, V, p.g.batch) ||
             tile_preferred(p.g.ndim, p.nl, p.nn, V, p.g.batch))
             P2.kernel = PF_KERNEL_LDS;
-        else if (any_fused_preferred(p.g.ndim, p.nl, p.nn, false, P2.storage))
+        else if (any_fused_preferred(p.g.ndim, p.nl, p.nn, false, P2.storage, p.tail))
             P2.kernel = PF_KERNEL_FUSED;
         else
             P2.kernel = PF_KERNEL_TWO_PASS;

@@ -52,29 +52,118 @@ constexpr int GTHREADS = GX * (GY + 2);    // owned rows, the halo row, the halo
 // before every leaf), and with 16-bit state only for an even ni (a packed
 // pair of flows never straddles the two kinds).  An identity slot's grad U is
 // grad u_L and its excess goes to d_L alone: the values the dense products
-// give (every other term is an exact zero), without the products.
-template <int NLMAX, int NI, bool TAIL>
+// give (every other term is an exact zero), without the products.  EXACT
+// builds serve graphs that fill every slot (nl = NLMAX, and nn - nl = NI with
+// TAIL or nn = NI without): slot s is node s and every slot is valid, known
+// at compile time.
+template <int NLMAX, int NI, bool TAIL, bool EXACT>
 struct Slots {
     static constexpr int N = TAIL ? NI + NLMAX : NI;
     static __device__ __forceinline__ bool tail(int s) { return TAIL && s >= NI; }
     static __device__ __forceinline__ int node(const StepArgs &a, int s) {
+        if constexpr (EXACT) return s;
         return tail(s) ? (a.nn - a.nl) + (s - NI) : s;
     }
     static __device__ __forceinline__ bool valid(const StepArgs &a, int s) {
+        if constexpr (EXACT) return true;
         return tail(s) ? s - NI < a.nl : s < (TAIL ? a.nn - a.nl : a.nn);
     }
 };
+
+// Start of field f (counted over problems and fields) of a [B][F][V] array
+// of 4-byte words, formed where it is used from the array's start and a
+// field size made opaque by an empty asm statement: otherwise the compiler
+// keeps the start of every field the pass touches live across the plane loop
+// (about 70 with 16 flows, more than a wavefront's scalar registers) and
+// reloads the spilled ones from lanes of a vector register at every use.
+__device__ __forceinline__ size_t opaque_size(size_t v) {
+    __asm__ volatile("" : "+s"(v));
+    return v;
+}
+template <typename W>
+__device__ __forceinline__ const W *fld(const void *base, int f, size_t V) {
+    return static_cast<const W *>(base) + (size_t)(unsigned)f * opaque_size(V);
+}
+template <typename W>
+__device__ __forceinline__ W *fld_w(void *base, int f, size_t V) {
+    return static_cast<W *>(base) + (size_t)(unsigned)f * opaque_size(V);
+}
+
+// Component k of flow A at voxel uv (ld_q with the start formed by fld; A
+// clamped into the graph the same way); with 16-bit state the packed word of
+// the node pair (A, A + 1), A even, whose halves the caller unpacks (a slot's
+// node has the slot's parity: every build's dense count and, with 16-bit
+// state, the internal node count are even; a pair past the graph reads some
+// valid word, its values unused).  Then the stores of st_q2 / st_ell2.
+template <bool EXACT>
+__device__ __forceinline__ uint32_t fl_ld_q_word(const StepArgs &a, int b, int A, int k, size_t V,
+                                                 unsigned uv) {
+    const int np = (a.nn + 1) / 2, P = A >> 1;
+    const uint32_t *p = fld<uint32_t>(a.q_in, (b * np + (EXACT || P < np ? P : np - 1)) * 3 + k, V);
+    return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(p) + uv * 4u);
+}
+__device__ __forceinline__ float fl_ld_q(const StepArgs &a, int b, int A, int k, size_t V, unsigned uv) {
+    return ldf(fld<float>(a.q_in, (b * a.nn + (A < a.nn ? A : a.nn - 1)) * 3 + k, V), uv);
+}
+// (EXACT: A + 1 < nn and L + 1 < nl hold, every build's counts being even)
+template <typename T, bool EXACT>
+__device__ __forceinline__ void fl_st_q2(const StepArgs &a, int b, int A, int k, size_t V, unsigned uv,
+                                         float lo, float hi) {
+    if constexpr (kPacked<T>) {
+        if (EXACT || A < a.nn) {
+            uint32_t *p = fld_w<uint32_t>(a.q_out, (b * ((a.nn + 1) / 2) + (A >> 1)) * 3 + k, V);
+            *reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(p) + uv * 4u) =
+                pack2(lo, EXACT || A + 1 < a.nn ? hi : 0.f, static_cast<const T *>(nullptr));
+        }
+    } else {
+        if (EXACT || A < a.nn) sto(fld_w<float>(a.q_out, (b * a.nn + A) * 3 + k, V), uv, lo);
+        if (EXACT || A + 1 < a.nn) sto(fld_w<float>(a.q_out, (b * a.nn + A + 1) * 3 + k, V), uv, hi);
+    }
+}
+template <typename T, bool EXACT>
+__device__ __forceinline__ void fl_st_ell2(const StepArgs &a, int b, int L, size_t V, unsigned uv,
+                                           float lo, float hi) {
+    if constexpr (kPacked<T>) {
+        if (EXACT || L < a.nl) {
+            uint32_t *p = fld_w<uint32_t>(a.ell_out, b * ((a.nl + 1) / 2) + (L >> 1), V);
+            *reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(p) + uv * 4u) =
+                pack2(lo, EXACT || L + 1 < a.nl ? hi : 0.f, static_cast<const T *>(nullptr));
+        }
+    } else {
+        if (EXACT || L < a.nl) sto(fld_w<float>(a.ell_out, b * a.nl + L, V), uv, lo);
+        if (EXACT || L + 1 < a.nl) sto(fld_w<float>(a.ell_out, b * a.nl + L + 1, V), uv, hi);
+    }
+}
+
+// entropic_step (the same expressions in the same order) with the label
+// count known at compile time in EXACT builds.
+template <int NLMAX, bool EXACT>
+__device__ __forceinline__ void fl_entropic_step(const StepArgs &a, const float (&d)[NLMAX],
+                                                 float (&ell)[NLMAX]) {
+    float m = -INFINITY;
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L) {
+        ell[L] = EXACT || L < a.nl ? fmaf(-d[L], a.inv_c, ell[L]) : -INFINITY;
+        m = fmaxf(m, ell[L]);
+    }
+    float sum = 0.f;
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L) sum += __expf(ell[L] - m);
+    const float ls = __logf(sum);
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L) ell[L] = (ell[L] - m) - ls;
+}
 
 // Flow step of iteration k at voxel (x, y, z): the labels of iteration k at
 // the voxel (returned in e0, as stored) and at x + e_k, the old flows at the
 // voxel and the capacities; returns the new flows of every slot after a
 // round trip through the storage type (what a later load returns; 0 in a
 // slot past the graph) and stores them when `store`.
-template <int NLMAX, int NI, bool TAIL, typename T>
+template <int NLMAX, int NI, bool TAIL, bool EXACT, typename T>
 __device__ __forceinline__ void flow_point(const StepArgs &a, int b, int x, int y, int z, bool store,
                                            float (&e0)[NLMAX],
-                                           float (&pr)[Slots<NLMAX, NI, TAIL>::N][3]) {
-    using SL = Slots<NLMAX, NI, TAIL>;
+                                           float (&pr)[Slots<NLMAX, NI, TAIL, EXACT>::N][3]) {
+    using SL = Slots<NLMAX, NI, TAIL, EXACT>;
     constexpr int NS = SL::N;
     const size_t V = (size_t)a.V;
     const unsigned uv = (unsigned)((z * a.ny + y) * a.nx + x);
@@ -91,8 +180,19 @@ __device__ __forceinline__ void flow_point(const StepArgs &a, int b, int x, int 
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int A = SL::valid(a, s) ? SL::node(a, s) : a.nn - 1;
+        if constexpr (kPacked<T>) {
+            if (s % 2 == 0) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) qv[s][k] = ld_q<T, 3>(a.q_in, b, a.nn, A, k, V, uv);
+                for (int k = 0; k < 3; ++k) {
+                    const uint32_t w = fl_ld_q_word<EXACT>(a, b, SL::node(a, s), k, V, uv);
+                    qv[s][k] = half_of(w, 0, static_cast<const T *>(nullptr));
+                    qv[s + 1][k] = half_of(w, 1, static_cast<const T *>(nullptr));
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) qv[s][k] = fl_ld_q(a, b, A, k, V, uv);
+        }
         sv[s] = smooth(a, b, A, (int)uv);
     }
     float gu[NLMAX][3];
@@ -126,7 +226,7 @@ __device__ __forceinline__ void flow_point(const StepArgs &a, int b, int x, int 
                 if (SL::valid(a, s)) {
 #pragma unroll
                     for (int k = 0; k < 3; ++k)
-                        st_q2<T, 3>(a.q_out, b, a.nn, SL::node(a, s), k, V, uv, p[0][k], p[1][k]);
+                        fl_st_q2<T, EXACT>(a, b, SL::node(a, s), k, V, uv, p[0][k], p[1][k]);
                 }
             } else {
 #pragma unroll
@@ -134,7 +234,7 @@ __device__ __forceinline__ void flow_point(const StepArgs &a, int b, int x, int 
                     if (SL::valid(a, s + j)) {
 #pragma unroll
                         for (int k = 0; k < 3; ++k)
-                            sto(field_w<float>(a.q_out, b, a.nn * 3, SL::node(a, s + j) * 3 + k, V), uv,
+                            sto(fld_w<float>(a.q_out, (b * a.nn + SL::node(a, s + j)) * 3 + k, V), uv,
                                 p[j][k]);
                     }
                 }
@@ -147,9 +247,9 @@ __device__ __forceinline__ void flow_point(const StepArgs &a, int b, int x, int 
     }
 }
 
-template <int NLMAX, int NI, bool TAIL, typename T>
+template <int NLMAX, int NI, bool TAIL, bool EXACT, typename T>
 __global__ __launch_bounds__(GTHREADS) void k_flow_label(StepArgs a, FusedGeom g) {
-    using SL = Slots<NLMAX, NI, TAIL>;
+    using SL = Slots<NLMAX, NI, TAIL, EXACT>;
     constexpr int NS = SL::N;
     // new flows' x and y components: [slot][component][row + 1][column + 1],
     // row 0 the halo row y0 - 1 and column 0 the halo column x0 - 1
@@ -187,7 +287,7 @@ __global__ __launch_bounds__(GTHREADS) void k_flow_label(StepArgs a, FusedGeom g
     for (int s = 0; s < NS; ++s) pzb[s] = 0.f;
     if (own && zs > 0) {
         float e0[NLMAX], pr[NS][3];
-        flow_point<NLMAX, NI, TAIL, T>(a, b, xa, ya, zs - 1, false, e0, pr);
+        flow_point<NLMAX, NI, TAIL, EXACT, T>(a, b, xa, ya, zs - 1, false, e0, pr);
 #pragma unroll
         for (int s = 0; s < NS; ++s) pzb[s] = pr[s][2];
     }
@@ -196,7 +296,7 @@ __global__ __launch_bounds__(GTHREADS) void k_flow_label(StepArgs a, FusedGeom g
         float e0[NLMAX], pz[NS], dl[NLMAX];
         if (va) {
             float pr[NS][3];
-            flow_point<NLMAX, NI, TAIL, T>(a, b, xa, ya, z, own, e0, pr);
+            flow_point<NLMAX, NI, TAIL, EXACT, T>(a, b, xa, ya, z, own, e0, pr);
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 lq[s][0][lr][lc] = pr[s][0];
@@ -208,29 +308,36 @@ __global__ __launch_bounds__(GTHREADS) void k_flow_label(StepArgs a, FusedGeom g
             const unsigned uv = (unsigned)((z * a.ny + ya) * a.nx + xa);
 #pragma unroll
             for (int L = 0; L < NLMAX; ++L)
-                dl[L] = ldf(field<float>(a.D, b, a.nl, L < a.nl ? L : a.nl - 1, V), uv);
+                dl[L] = ldf(fld<float>(a.D, b * a.nl + (EXACT || L < a.nl ? L : a.nl - 1), V), uv);
         }
         __syncthreads();
         // label step of iteration k + 1 (label_body's expressions and order:
         // the nodes in order, the internal ones first)
         if (own) {
             const unsigned uv = (unsigned)((z * a.ny + ya) * a.nx + xa);
-            const bool bwd[3] = {xa > 0, ya > 0, z > 0};
-            const bool fwd[3] = {xa < a.nx - 1, ya < a.ny - 1, z < a.nz - 1};
+            const bool bwd[2] = {xa > 0, ya > 0};
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                const float q0[3] = {lq[s][0][lr][lc], lq[s][1][lr][lc], pz[s]};
-                const float qm[3] = {lq[s][0][lr][lc - 1], lq[s][1][lr - 1][lc], pzb[s]};
-                const float dv = div_from<3>(q0, qm, fwd, bwd);
+                // div_from's sum in its order; the forward terms need no
+                // select (a new flow's component is +0 where the voxel is
+                // last on its axis) nor does q_z below the first plane (pzb
+                // starts at +0)
+                float dv = 0.f;
+                dv += lq[s][0][lr][lc];
+                dv -= bwd[0] ? lq[s][0][lr][lc - 1] : 0.f;
+                dv += lq[s][1][lr][lc];
+                dv -= bwd[1] ? lq[s][1][lr - 1][lc] : 0.f;
+                dv += pz[s];
+                dv -= pzb[s];
                 if (SL::tail(s)) {
                     dl[s - NI] += dv;
                 } else {
                     add_excess<NLMAX, false>(a, dl, s, dv);
                 }
             }
-            entropic_step<NLMAX>(a, dl, e0);
+            fl_entropic_step<NLMAX, EXACT>(a, dl, e0);
 #pragma unroll
-            for (int L = 0; L < NLMAX; L += 2) st_ell2<T>(a.ell_out, b, a.nl, L, V, uv, e0[L], e0[L + 1]);
+            for (int L = 0; L < NLMAX; L += 2) fl_st_ell2<T, EXACT>(a, b, L, V, uv, e0[L], e0[L + 1]);
 #pragma unroll
             for (int s = 0; s < NS; ++s) pzb[s] = pz[s];
         }
@@ -254,16 +361,30 @@ bool flow_label_tail_supported(int nl, int nn, int storage) {
     return storage == PF_FP32 || ni % 2 == 0;
 }
 
+// Graphs whose end-labels are the last nodes and fill every slot of a build
+// with identity slots (the EXACT forms: 4, 8, 12 or 16 leaves under 4
+// internal nodes, 8 or 12 leaves under 8).
+static bool flow_label_tail_exact(int nl, int nn) {
+    const int ni = nn - nl;
+    return (ni == 4 && nl % 4 == 0 && nl <= 16 && nn <= 16) || (ni == 8 && (nl == 8 || nl == 12) && nn <= 16);
+}
+
 // PF_KERNEL_AUTO takes this pass where it measured faster than the two-pass
 // kernels on MI355X: float32 state with more than 8 flows (per iteration:
-// DAGMF 256x512x512 9.30 against 10.9-11.5 ms, HMF 128x256x256 0.798 against
-// 0.843 ms; the 7-flow Ishikawa chain 0.64 against 0.62 ms).  With 16-bit
-// state the two-pass kernels stay ahead (DAGMF bf16 6.29 against 5.61 ms):
-// this pass issues about 1.3x the instructions of the two passes (halo
-// recomputation) at one block per compute unit, the two passes are bound by
-// memory bandwidth.
-bool flow_label_preferred(int nd, int nl, int nn, bool identity, int storage) {
-    return storage == PF_FP32 && nn > 8 && flow_label_supported(nd, nl, nn, identity);
+// DAGMF 256x512x512 9.29 against 10.6-11.5 ms, HMF 128x256x256 0.796 against
+// 0.847 ms; the 7-flow Ishikawa chain 0.62 against 0.62 ms), and every
+// storage type for the EXACT forms (DAGMF bf16 5.00 against 5.60 ms, fp16
+// 5.00 against 5.73; random DAGs of 4/8, 8/8, 4/12 and 4/4 internal nodes /
+// leaves at 128x256x256, bf16: 1.09, 1.04, 1.09 and 1.05x faster, fp32:
+// 1.12-1.15x).  Otherwise, with 16-bit state, the two-pass kernels stay
+// ahead (HMF bf16 0.564 against 0.490 ms): this pass issues more
+// instructions than the two passes (halo recomputation, and the slot and
+// label masks of graphs that do not fill the build) at one block per
+// compute unit, while the two passes are bound by memory bandwidth.
+bool flow_label_preferred(int nd, int nl, int nn, bool identity, int storage, bool tail) {
+    if (!flow_label_supported(nd, nl, nn, identity)) return false;
+    if (tail && flow_label_tail_exact(nl, nn) && flow_label_tail_supported(nl, nn, storage)) return true;
+    return storage == PF_FP32 && nn > 8;
 }
 
 // About four blocks per compute unit over the pass, chunks of at least 16
@@ -276,8 +397,12 @@ hipError_t launch_flow_label(const StepArgs &a, int storage, bool tail, hipStrea
     if (g.blocks <= 0 || g.blocks > 0x7fffffffL) return hipErrorInvalidValue;
     const int ni = a.nn - a.nl;
     tail = tail && flow_label_tail_supported(a.nl, a.nn, storage);
+    // tail builds also come in an EXACT form for graphs that fill every slot
     auto go = [&]<int NL, int NI, bool TL, typename T>() {
-        k_flow_label<NL, NI, TL, T><<<(unsigned)g.blocks, GTHREADS, 0, s>>>(a, g);
+        if (TL && a.nl == NL && a.nn - a.nl == NI)
+            k_flow_label<NL, NI, TL, TL, T><<<(unsigned)g.blocks, GTHREADS, 0, s>>>(a, g);
+        else
+            k_flow_label<NL, NI, TL, false, T><<<(unsigned)g.blocks, GTHREADS, 0, s>>>(a, g);
         return hipGetLastError();
     };
     auto by = [&]<typename T>() -> hipError_t {

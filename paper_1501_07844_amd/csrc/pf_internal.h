@@ -143,11 +143,12 @@ FusedGeom fused2_geometry(const StepArgs &a);
 hipError_t launch_flow_label(const StepArgs &a, int storage, bool tail, hipStream_t s);
 bool flow_label_supported(int nd, int nl, int nn, bool identity);
 bool flow_label_tail_supported(int nl, int nn, int storage);
-bool flow_label_preferred(int nd, int nl, int nn, bool identity, int storage);
-// PF_KERNEL_AUTO's choice of a one-pass-per-iteration kernel (either kind)
-inline bool any_fused_preferred(int nd, int nl, int nn, bool identity, int storage) {
+bool flow_label_preferred(int nd, int nl, int nn, bool identity, int storage, bool tail);
+// PF_KERNEL_AUTO's choice of a one-pass-per-iteration kernel (either kind);
+// `tail` as for launch_flow_label (assumed by the queries that have no graph)
+inline bool any_fused_preferred(int nd, int nl, int nn, bool identity, int storage, bool tail) {
     return fused_preferred(nd, nl, nn, identity, storage) ||
-           flow_label_preferred(nd, nl, nn, identity, storage);
+           flow_label_preferred(nd, nl, nn, identity, storage, tail);
 }
 FusedGeom flow_label_geometry(const StepArgs &a);
 // tiles of width x rows voxels, z chunks, problems (the z-marching kernels);

@@ -181,6 +181,11 @@ def flow_label_cases():
         ("ishikawa3d 8 levels", synth.ishikawa_levels(shape=(17, 7, 35), n_levels=7), 3, 0),
         ("dag3d nl16 nn16", synth.random_problem(6, (9, 8, 34), 3, big, s_mode="node_scalar"), 2, 0),
         ("tree3d nl2 nn3 thin", synth.random_problem(7, (3, 2, 40), 3, tiny, s_mode="node_field"), 3, 0),
+        # graphs filling every slot of a tail build (the EXACT forms)
+        ("dag3d nl4 nn8 B2 exact", synth.random_problem(8, (21, 10, 70), 3, synth.random_dag(rng, 4, 4),
+                                                        batch=2, s_mode="node_field"), 4, 3),
+        ("dag3d nl8 nn12 exact", synth.random_problem(9, (12, 9, 66), 3, synth.random_dag(rng, 4, 8),
+                                                      s_mode="shared_field"), 3, 0),
     ]
 
 

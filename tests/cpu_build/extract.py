@@ -32,7 +32,8 @@ def main(out):
     fk = f[:f.index("template <int ND, typename T, typename F>\nhipError_t fused_bucket")]
     fk += "\n}  // namespace\n" + cut(f, "bool fused_supported(", "hipError_t launch_fused(")
     fk += "\n}  // namespace pf\n"
-    fl = open(os.path.join(SRC, "pf_flowlabel.hip")).read()
+    fl = open(os.path.join(SRC, "pf_flowlabel.hip")).read().replace(
+        '__asm__ volatile("" : "+s"(v));', '__asm__ volatile("" : "+r"(v));')
     flk = fl[:fl.index("// ----------------------------------------------------------- dispatch ----")]
     flk += "\n}  // namespace\n" + cut(fl, "bool flow_label_supported(", "hipError_t launch_flow_label(")
     flk += "\n}  // namespace pf\n"

@@ -163,7 +163,10 @@ hipError_t launch_flow_label(const StepArgs &a, int st, bool tail, hipStream_t) 
     const int ni = a.nn - a.nl;
     tail = tail && flow_label_tail_supported(a.nl, a.nn, st);
     auto go = [&]<int NL, int NI, bool TL, typename T>() {
-        run_grid(dim3((unsigned)g.blocks), GTHREADS, true, [&] { k_flow_label<NL, NI, TL, T>(a, g); });
+        if (TL && a.nl == NL && a.nn - a.nl == NI)
+            run_grid(dim3((unsigned)g.blocks), GTHREADS, true, [&] { k_flow_label<NL, NI, TL, TL, T>(a, g); });
+        else
+            run_grid(dim3((unsigned)g.blocks), GTHREADS, true, [&] { k_flow_label<NL, NI, TL, false, T>(a, g); });
         return 0;
     };
     auto by = [&]<typename T>() -> hipError_t {

@@ -225,6 +225,13 @@ FLOW_LABEL_CASES = {
         38, (5, 7, 133), 3, synth.random_tree(np.random.default_rng(38), 1, 2),
         s_mode="shared_field", kind="hmf"), 3),
     "dagmf_blobs_40x70x130_chunks": (lambda: synth.dagmf_blobs(shape=(40, 70, 130)), 0),
+    # graphs that fill every slot of a build with identity slots (the exact forms)
+    "dag_nl4_nn8_B2_exact": (lambda: synth.random_problem(
+        39, (11, 17, 75), 3, synth.random_dag(np.random.default_rng(39), 4, 4), batch=2,
+        s_mode="node_field"), 5),
+    "dag_nl8_nn12_exact": (lambda: synth.random_problem(
+        40, (19, 9, 66), 3, synth.random_dag(np.random.default_rng(40), 4, 8),
+        s_mode="shared_field"), 0),
 }
 
 
