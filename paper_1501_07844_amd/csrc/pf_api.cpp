@@ -431,6 +431,38 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream, bool stat
         if (flag & 1) return fail(PF_ENONFINITE, "D holds NaN or Inf");
         if (flag & 2) return fail(PF_ENONFINITE, "S holds NaN, Inf or a negative value");
     }
+    // iterations per launch sequence (up to the next gap check for the LDS
+    // kernels and the flow-then-label passes, two for a pair of the
+    // two-iteration kernel) and the state buffer flips they make
+    const int kmax_tile = want_tile ? tile_geometry(a.nx, a.ny, a.B, a.nn).k : 1;
+    auto step_at = [&](int it) {
+        const bool pair = want_fused2 && it + 1 < P->iters &&
+                          !(P->gap_every > 0 && (it + 1) % P->gap_every == 0);
+        if (want_lds || want_tile || want_fl)
+            return P->gap_every > 0 ? std::min(P->iters - it, P->gap_every - it % P->gap_every)
+                                    : P->iters - it;
+        return pair ? 2 : 1;
+    };
+    auto flips_of = [&](int step) {
+        if (want_tile) return (step + kmax_tile - 1) / kmax_tile;
+        if (want_fl) return step - 1;
+        return want_fused ? 1 : 0;
+    };
+    // A fresh solve that runs to its end starts in the buffer that makes it
+    // end in the first one (where a warm start looks for the state), so that
+    // no copy is needed at the end.
+    int cur = 0;
+    if (!P->warm_start && !(P->gap_tol > 0.0)) {
+        int flips = 0;
+        for (int it = 0; it < P->iters;) {
+            const int st = step_at(it);
+            flips += flips_of(st);
+            it += st;
+        }
+        cur = flips & 1;
+    }
+    a.ell_in = a.ell_out = ell[cur];
+    a.q_in = a.q_out = q[cur];
     if (!P->warm_start) {
         if ((e = launch_init(a, nd, P->storage, -logf((float)p.nl), stream)) != hipSuccess)
             return hip_fail(e, "init");
@@ -449,21 +481,15 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream, bool stat
     };
 
     Timer timer;
-    int cur = 0;
     const TapeGeom tg = tape_geom(p.g, p.nl, p.nn, P->iters, P->ckpt_every);
     const size_t n_ell = (size_t)a.B * a.nl * a.V, n_q = (size_t)a.B * a.nn * nd * a.V;
     int timed_iters = 0;
     for (int it = 0; it < P->iters;) {
-        // two iterations in one pass unless a gap check falls after the first
-        const bool pair = want_fused2 && it + 1 < P->iters &&
-                          !(P->gap_every > 0 && (it + 1) % P->gap_every == 0);
-        // the LDS kernel and the flow-then-label passes run every iteration up
-        // to the next gap check
-        const int step = (want_lds || want_tile || want_fl)
-                             ? (P->gap_every > 0 ? std::min(P->iters - it,
-                                                            P->gap_every - it % P->gap_every)
-                                                 : P->iters - it)
-                             : pair ? 2 : 1;
+        // two iterations in one pass unless a gap check falls after the first;
+        // the LDS kernels and the flow-then-label passes run every iteration
+        // up to the next gap check
+        const int step = step_at(it);
+        const bool pair = want_fused2 && step == 2;
         if (P->tape && it % P->ckpt_every == 0) {
             char *slot = static_cast<char *>(P->tape) + (size_t)(it / P->ckpt_every) * tg.slot_bytes;
             if ((e = launch_copy_f(static_cast<const float *>(ell[0]), reinterpret_cast<float *>(slot),
@@ -487,7 +513,7 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream, bool stat
                 return hip_fail(e, "LDS-resident iterations");
         } else if (want_tile) {
             // launches of up to k iterations each, ping-pong
-            const int kmax = tile_geometry(a.nx, a.ny, a.B, a.nn).k;
+            const int kmax = kmax_tile;
             for (int j = 0; j < step; j += kmax) {
                 a.ell_in = ell[cur];
                 a.q_in = q[cur];
