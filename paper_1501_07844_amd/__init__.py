@@ -310,8 +310,11 @@ def solve_potts(D, S, *, c: float, tau: float, iters: int, **kw) -> SolveResult:
     [B][Z][Y][X] (shared) or [B][n][Z][Y][X] (per label).  ``kernel``:
     "auto" (see ``auto_kernel``), "two_pass", "fused" (one pass per
     iteration), "fused2" (one pass per two iterations; 3-D, n <= 8) or
-    "lds" (2-D problems whose state fits in LDS: every iteration up to the
-    next gap check in one launch); all give the same result bit for bit."""
+    "lds" (2-D, n <= 8: iterations in LDS, whole problems per block for
+    batches of 8 or more that fit, tiles with ghost zones otherwise); all
+    give the same result bit for bit.  ``final_energy=True`` (the default)
+    reads the energy back and synchronises the stream; with it off and no
+    gap checks the call is asynchronous."""
     n = int(D.shape[1])
     return _solve(library().solve_potts, D, S, n, n, n_labels=n, c=c, tau=tau, iters=iters, **kw)
 
