@@ -489,6 +489,30 @@ def test_full_size_sampled_one_step(kernel):
     assert worst_u <= 1e-5 and worst_q <= 1e-5
 
 
+def test_full_size_dagmf_auto_equals_two_pass_bitwise():
+    """The benchmark's workload and launch configuration (DAGMF 256x512x512,
+    AUTO: the flow-then-label pass in its exact build) against the two-pass
+    kernels (checked against the reference at this size by the sampled
+    one-step test below), 5 iterations from the initial state, in fp32 and
+    bf16 state: every output and the energies bit for bit."""
+    p = synth.dagmf_blobs(iters=5)
+    D = torch.from_numpy(p.D).cuda()
+    for storage in ("fp32", "bf16"):
+        assert pf.auto_kernel(p.shape, p.n_leaf, p.n_node, 3, storage, identity=False) == "fused"
+        kw = dict(c=p.c, tau=p.tau, iters=p.iters, ndim=3, s_mode=p.s_mode, storage=storage,
+                  return_q=True)
+        print(f"[full-size auto] dagmf 256x512x512 {storage}", flush=True)
+        a = pf.solve_dagmf(D, p.S, p.graph, kernel="two_pass", **kw)
+        ua, qa, la, ea = a.u.clone(), a.q.clone(), a.labels.clone(), (a.energy, a.dual)
+        del a
+        torch.cuda.empty_cache()
+        b = pf.solve_dagmf(D, p.S, p.graph, **kw)
+        assert torch.equal(ua, b.u) and torch.equal(qa, b.q) and torch.equal(la, b.labels)
+        assert ea == (b.energy, b.dual)
+        del ua, qa, la, b
+        torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("storage", ["fp32", "bf16"])
 @pytest.mark.parametrize("name", ["hmf", "dagmf"])
 def test_full_size_graph_sampled_one_step(name, storage):
