@@ -78,8 +78,9 @@ typedef enum {
                                 Ishikawa chain) of 9 to 16 flows and at most 16
                                 leaves with fp32 state, and in every storage type
                                 for 3-D graphs whose end-labels are the last nodes,
-                                under 4 internal nodes with 4, 8, 12 or 16 leaves
-                                or under 8 with 8 or 12; two-pass otherwise */
+                                under 4 internal nodes with 4, 8, 12 or 16 leaves,
+                                under 8 with 8 or 12, or under 3 with 8; two-pass
+                                otherwise */
     PF_KERNEL_TWO_PASS = 1,  /* label pass then flow pass, state updated in place */
     PF_KERNEL_FUSED = 2,     /* one pass per iteration, state ping-ponged (at most 16
                                 leaves and 16 flows; 3-D label graphs run the flow

@@ -55,17 +55,19 @@ constexpr int GTHREADS = GX * (GY + 2);    // owned rows, the halo row, the halo
 // give (every other term is an exact zero), without the products.  EXACT
 // builds serve graphs that fill every slot (nl = NLMAX, and nn - nl = NI with
 // TAIL or nn = NI without): slot s is node s and every slot is valid, known
-// at compile time.
+// at compile time; then a slot pair is a node pair whatever the parity of
+// NI, and an odd slot count gets one padding slot (NP), invalid.
 template <int NLMAX, int NI, bool TAIL, bool EXACT>
 struct Slots {
     static constexpr int N = TAIL ? NI + NLMAX : NI;
+    static constexpr int NP = (N + 1) / 2 * 2;
     static __device__ __forceinline__ bool tail(int s) { return TAIL && s >= NI; }
     static __device__ __forceinline__ int node(const StepArgs &a, int s) {
         if constexpr (EXACT) return s;
         return tail(s) ? (a.nn - a.nl) + (s - NI) : s;
     }
     static __device__ __forceinline__ bool valid(const StepArgs &a, int s) {
-        if constexpr (EXACT) return true;
+        if constexpr (EXACT) return s < N;
         return tail(s) ? s - NI < a.nl : s < (TAIL ? a.nn - a.nl : a.nn);
     }
 };
@@ -162,9 +164,9 @@ __device__ __forceinline__ void fl_entropic_step(const StepArgs &a, const float 
 template <int NLMAX, int NI, bool TAIL, bool EXACT, typename T>
 __device__ __forceinline__ void flow_point(const StepArgs &a, int b, int x, int y, int z, bool store,
                                            float (&e0)[NLMAX],
-                                           float (&pr)[Slots<NLMAX, NI, TAIL, EXACT>::N][3]) {
+                                           float (&pr)[Slots<NLMAX, NI, TAIL, EXACT>::NP][3]) {
     using SL = Slots<NLMAX, NI, TAIL, EXACT>;
-    constexpr int NS = SL::N;
+    constexpr int NS = SL::NP;
     const size_t V = (size_t)a.V;
     const unsigned uv = (unsigned)((z * a.ny + y) * a.nx + x);
     const bool h[3] = {x < a.nx - 1, y < a.ny - 1, z < a.nz - 1};
@@ -286,7 +288,7 @@ __global__ __launch_bounds__(GTHREADS) void k_flow_label(StepArgs a, FusedGeom g
 #pragma unroll
     for (int s = 0; s < NS; ++s) pzb[s] = 0.f;
     if (own && zs > 0) {
-        float e0[NLMAX], pr[NS][3];
+        float e0[NLMAX], pr[SL::NP][3];
         flow_point<NLMAX, NI, TAIL, EXACT, T>(a, b, xa, ya, zs - 1, false, e0, pr);
 #pragma unroll
         for (int s = 0; s < NS; ++s) pzb[s] = pr[s][2];
@@ -295,7 +297,7 @@ __global__ __launch_bounds__(GTHREADS) void k_flow_label(StepArgs a, FusedGeom g
     for (int z = zs; z < ze; ++z) {
         float e0[NLMAX], pz[NS], dl[NLMAX];
         if (va) {
-            float pr[NS][3];
+            float pr[SL::NP][3];
             flow_point<NLMAX, NI, TAIL, EXACT, T>(a, b, xa, ya, z, own, e0, pr);
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
@@ -354,19 +356,21 @@ bool flow_label_supported(int nd, int nl, int nn, bool identity) {
 }
 
 // Builds with identity slots: at most 8 internal nodes (and 4 with more than
-// 12 leaves), an even count of them with 16-bit state.
+// 12 leaves), an even count of them with 16-bit state unless the graph fills
+// an exact build (3 internal nodes over 8 leaves: the HMF tree).
 bool flow_label_tail_supported(int nl, int nn, int storage) {
     const int ni = nn - nl;
     if (ni < 0 || ni > 8 || (ni > 4 && nl > 12)) return false;
-    return storage == PF_FP32 || ni % 2 == 0;
+    return storage == PF_FP32 || ni % 2 == 0 || (ni == 3 && nl == 8);
 }
 
 // Graphs whose end-labels are the last nodes and fill every slot of a build
 // with identity slots (the EXACT forms: 4, 8, 12 or 16 leaves under 4
-// internal nodes, 8 or 12 leaves under 8).
+// internal nodes, 8 or 12 leaves under 8, 8 leaves under 3).
 static bool flow_label_tail_exact(int nl, int nn) {
     const int ni = nn - nl;
-    return (ni == 4 && nl % 4 == 0 && nl <= 16 && nn <= 16) || (ni == 8 && (nl == 8 || nl == 12) && nn <= 16);
+    return (ni == 4 && nl % 4 == 0 && nl <= 16 && nn <= 16) || (ni == 8 && (nl == 8 || nl == 12) && nn <= 16) ||
+           (ni == 3 && nl == 8);
 }
 
 // PF_KERNEL_AUTO takes this pass where it measured faster than the two-pass
@@ -374,13 +378,15 @@ static bool flow_label_tail_exact(int nl, int nn) {
 // DAGMF 256x512x512 9.29 against 10.6-11.5 ms, HMF 128x256x256 0.796 against
 // 0.847 ms; the 7-flow Ishikawa chain 0.62 against 0.62 ms), and every
 // storage type for the EXACT forms (DAGMF bf16 5.00 against 5.60 ms, fp16
-// 5.00 against 5.73; random DAGs of 4/8, 8/8, 4/12 and 4/4 internal nodes /
+// 5.00 against 5.73; the HMF tree bf16 0.452 against 0.483 ms, fp32 0.747
+// against 0.836; random DAGs of 4/8, 8/8, 4/12 and 4/4 internal nodes /
 // leaves at 128x256x256, bf16: 1.09, 1.04, 1.09 and 1.05x faster, fp32:
 // 1.12-1.15x).  Otherwise, with 16-bit state, the two-pass kernels stay
-// ahead (HMF bf16 0.564 against 0.490 ms): this pass issues more
-// instructions than the two passes (halo recomputation, and the slot and
-// label masks of graphs that do not fill the build) at one block per
-// compute unit, while the two passes are bound by memory bandwidth.
+// ahead (the HMF tree in a non-exact build: 0.564 against 0.490 ms): this
+// pass issues more instructions than the two passes (halo recomputation,
+// and the slot and label masks of graphs that do not fill the build) at one
+// block per compute unit, while the two passes are bound by memory
+// bandwidth.
 bool flow_label_preferred(int nd, int nl, int nn, bool identity, int storage, bool tail) {
     if (!flow_label_supported(nd, nl, nn, identity)) return false;
     if (tail && flow_label_tail_exact(nl, nn) && flow_label_tail_supported(nl, nn, storage)) return true;
@@ -398,15 +404,19 @@ hipError_t launch_flow_label(const StepArgs &a, int storage, bool tail, hipStrea
     const int ni = a.nn - a.nl;
     tail = tail && flow_label_tail_supported(a.nl, a.nn, storage);
     // tail builds also come in an EXACT form for graphs that fill every slot
+    // (a tail build with an odd internal count exists only in the EXACT form)
     auto go = [&]<int NL, int NI, bool TL, typename T>() {
         if (TL && a.nl == NL && a.nn - a.nl == NI)
             k_flow_label<NL, NI, TL, TL, T><<<(unsigned)g.blocks, GTHREADS, 0, s>>>(a, g);
-        else
+        else if constexpr (!(TL && NI % 2 == 1))
             k_flow_label<NL, NI, TL, false, T><<<(unsigned)g.blocks, GTHREADS, 0, s>>>(a, g);
+        else
+            return hipErrorInvalidValue;
         return hipGetLastError();
     };
     auto by = [&]<typename T>() -> hipError_t {
         if (tail) {
+            if (ni == 3 && a.nl == 8) return go.template operator()<8, 3, true, T>();
             if (ni <= 4 && a.nl <= 4) return go.template operator()<4, 4, true, T>();
             if (ni <= 4 && a.nl <= 8) return go.template operator()<8, 4, true, T>();
             if (ni <= 4 && a.nl <= 12) return go.template operator()<12, 4, true, T>();

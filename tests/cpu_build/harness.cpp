@@ -165,12 +165,15 @@ hipError_t launch_flow_label(const StepArgs &a, int st, bool tail, hipStream_t) 
     auto go = [&]<int NL, int NI, bool TL, typename T>() {
         if (TL && a.nl == NL && a.nn - a.nl == NI)
             run_grid(dim3((unsigned)g.blocks), GTHREADS, true, [&] { k_flow_label<NL, NI, TL, TL, T>(a, g); });
-        else
+        else if constexpr (!(TL && NI % 2 == 1))
             run_grid(dim3((unsigned)g.blocks), GTHREADS, true, [&] { k_flow_label<NL, NI, TL, false, T>(a, g); });
+        else
+            return 1;
         return 0;
     };
     auto by = [&]<typename T>() -> hipError_t {
         if (tail) {
+            if (ni == 3 && a.nl == 8) return go.template operator()<8, 3, true, T>();
             if (ni <= 4 && a.nl <= 4) return go.template operator()<4, 4, true, T>();
             if (ni <= 4 && a.nl <= 8) return go.template operator()<8, 4, true, T>();
             if (ni <= 4 && a.nl <= 12) return go.template operator()<12, 4, true, T>();

@@ -93,12 +93,13 @@ def test_auto_kernel_choice():
     assert pf.auto_kernel((1, 16, 16, 16), 8, 11, 3, identity=False) == "fused"
     assert pf.auto_kernel((1, 256, 512, 512), 12, 16, 3, identity=False) == "fused"
     # graphs that fill a build with identity slots (leaves last, 4 internal
-    # nodes and 4-16 leaves, or 8 and 8 or 12): the pass in every storage type
+    # nodes and 4-16 leaves, 8 and 8 or 12, 3 and 8): the pass in every storage type
     assert pf.auto_kernel((1, 256, 512, 512), 12, 16, 3, "bf16", identity=False) == "fused"
     assert pf.auto_kernel((1, 16, 16, 16), 4, 8, 3, "fp16", identity=False) == "fused"
     assert pf.auto_kernel((1, 16, 16, 16), 4, 8, 3, "fp32", identity=False) == "fused"
     assert pf.auto_kernel((1, 16, 16, 16), 8, 16, 3, "bf16", identity=False) == "fused"
-    assert pf.auto_kernel((1, 16, 16, 16), 8, 11, 3, "bf16", identity=False) == "two_pass"   # HMF tree
+    assert pf.auto_kernel((1, 16, 16, 16), 8, 11, 3, "bf16", identity=False) == "fused"      # HMF tree
+    assert pf.auto_kernel((1, 16, 16, 16), 7, 10, 3, "bf16", identity=False) == "two_pass"
     assert pf.auto_kernel((1, 16, 16, 16), 10, 14, 3, "bf16", identity=False) == "two_pass"
     assert pf.auto_kernel((1, 16, 16, 16), 16, 16, 3, "fp16", identity=False) == "two_pass"
     assert pf.auto_kernel((1, 16, 16, 16), 8, 7, 3, identity=False) == "two_pass"   # 7 flows
