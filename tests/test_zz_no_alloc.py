@@ -1,9 +1,9 @@
 """The static-scratch DAGMF solve (solve_dagmf_static, for callers that cannot
 allocate device memory) against solve_dagmf with a caller workspace: the same
 kernels run on the same inputs, so the results agree bit for bit.  Two calls
-in a row with the second smaller, a warm start from the static scratch, the
-LDS-resident kernels on a batch of 2-D problems, the size limit and the
-argument checks, all through the C ABI."""
+in a row with the second smaller, warm starts from the static scratch, the
+LDS-resident kernels on a batch of 2-D problems and in tiles on one, the
+size limit and the argument checks, all through the C ABI."""
 import ctypes as C
 
 import numpy as np
@@ -65,6 +65,16 @@ def test_static_scratch_warm_start_and_lds_batch():
     assert pf.auto_kernel(q.shape, q.n_leaf, q.n_node, 2, identity=False) == "lds"
     a, b = _both(q, 17, gap_every=5, gap_history_cap=4)
     _same(a, b)
+    # one 2-D problem: LDS tiles with ghost zones (ping-pong state), 21
+    # iterations at once against 13 then 8 more from the static scratch
+    t = synth.random_problem(44, (1, 40, 52), 2, dag, s_mode="node_field")
+    assert pf.auto_kernel(t.shape, t.n_leaf, t.n_node, 2, identity=False) == "lds"
+    Dt, St = device_inputs(t)
+    kt = dict(c=t.c, tau=t.tau, ndim=2, s_mode=t.s_mode, return_q=True)
+    full = pf.solve_dagmf(Dt, St, t.graph, iters=21, **kt)
+    pf.solve_dagmf_static(Dt, St, t.graph, iters=13, **kt)
+    rest = pf.solve_dagmf_static(Dt, St, t.graph, iters=8, warm_start=True, **kt)
+    assert torch.equal(full.u, rest.u) and torch.equal(full.q, rest.q)
 
 
 def _raw_params(**kw):
