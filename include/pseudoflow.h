@@ -287,9 +287,11 @@ size_t pf_backward_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t 
  * the reverse step: PF_KERNEL_TWO_PASS runs two kernels (projection adjoint,
  * then label adjoint), PF_KERNEL_FUSED one fused kernel (PF_EUNSUPPORTED
  * beyond 8 Potts labels in 2-D, 4 in 3-D, or 4 leaves / 8 flows on a 2-D
- * label graph; not for 3-D label graphs), PF_KERNEL_FUSED2 and
- * PF_KERNEL_LDS PF_EUNSUPPORTED, PF_KERNEL_AUTO the two kernels
- * (faster on MI355X).  Both give the same gradients bit for bit.  The tape
+ * label graph; not for 3-D label graphs; in 2-D with rows of up to 512
+ * voxels it marches along the rows), PF_KERNEL_FUSED2 and PF_KERNEL_LDS
+ * PF_EUNSUPPORTED, PF_KERNEL_AUTO the fused kernel where it marches rows and
+ * the two kernels otherwise (faster on MI355X).  Both give the same
+ * gradients bit for bit.  The tape
  * and the inputs must be those of the recorded call: the library cannot
  * check that.  Calls sharing a workspace must not overlap. */
 int pf_potts_backward(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,

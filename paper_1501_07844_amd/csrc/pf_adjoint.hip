@@ -23,7 +23,9 @@
 //     recomputed by two extra halo wavefronts, and along z the backward
 //     neighbour is the thread's own previous plane.  lbar and pbar are read
 //     from one buffer and written to another, since the halo points read
-//     values that the neighbouring blocks overwrite.
+//     values that the neighbouring blocks overwrite.  In 2-D (rows of up to
+//     512 voxels) a block instead spans whole rows and marches along y, with
+//     no halo points (k_adj_rows).
 // Both variants evaluate the same per-point expressions (ka_point, kb_point)
 // and give the same gradients bit for bit.
 
@@ -381,6 +383,80 @@ __global__ __launch_bounds__(RTHREADS) void k_adj_fused(StepArgs a, AdjArgs g, F
     }
 }
 
+// ------------------------------------------------- 2-D row march ---------
+
+// In 2-D the fused kernel above has no planes to march and spends two halo
+// wavefronts per 8-row tile.  Here a block spans every column of a problem
+// (one thread per column, one wavefront per 64 columns) and marches a chunk
+// of rows: KB at (x, y) takes the new pbar_x at x - 1 from its neighbour
+// thread through LDS (by row parity, one barrier per row) and the new pbar_y
+// at y - 1 from the thread's own previous row, so no point is computed twice
+// except KA on the row before a chunk.
+constexpr int ROW_COLS = 512;         // widest row a block spans
+
+template <int NLMAX, int NNMAX, bool IDENT>
+__global__ __launch_bounds__(ROW_COLS) void k_adj_rows(StepArgs a, AdjArgs g, int cy, int n_chunks) {
+    __shared__ float xs[2][NNMAX][ROW_COLS];       // new pbar_x of the row, by row parity
+    const int x = threadIdx.x;
+    const int ch = blockIdx.x % n_chunks;
+    const int b = blockIdx.x / n_chunks;
+    const bool vx = x < a.nx;
+    const int ys = ch * cy;
+    const int ye = min(a.ny, ys + cy);
+    const size_t V = (size_t)a.V;
+
+    float py[NNMAX];                 // new pbar_y on the row below
+#pragma unroll
+    for (int A = 0; A < NNMAX; ++A) py[A] = 0.f;
+    if (vx && ys > 0) {
+        float out[NNMAX][2], sb[NNMAX], e0[NLMAX], l0[NLMAX];
+        ka_point<2, NLMAX, NNMAX, IDENT>(a, g, b, Coord{x, ys - 1, 0},
+                                         (unsigned)((ys - 1) * a.nx + x), out, sb, e0, l0);
+#pragma unroll
+        for (int A = 0; A < NNMAX; ++A) py[A] = out[A][1];
+    }
+
+    for (int y = ys; y < ye; ++y) {
+        const int par = y & 1;
+        float out[NNMAX][2], sb[NNMAX], e0[NLMAX], l0[NLMAX], dacc[NLMAX], sacc[NNMAX];
+        const unsigned uv = (unsigned)(y * a.nx + x);
+        if (vx) {
+            load_dbar<NLMAX>(a, g, b, uv, dacc);
+            load_sbar<NNMAX>(a, g, b, uv, sacc);
+            ka_point<2, NLMAX, NNMAX, IDENT>(a, g, b, Coord{x, y, 0}, uv, out, sb, e0, l0);
+#pragma unroll
+            for (int A = 0; A < NNMAX; ++A) xs[par][A][x] = out[A][0];
+        }
+        __syncthreads();   // the row's new pbar_x is in LDS
+        if (vx) {
+            const bool fwd[3] = {x < a.nx - 1, y < a.ny - 1, false};
+            const bool bwd[3] = {x > 0, y > 0, false};
+            float p0[NNMAX][3], pm[NNMAX][3];
+#pragma unroll
+            for (int A = 0; A < NNMAX; ++A) {
+                p0[A][0] = out[A][0];
+                p0[A][1] = out[A][1];
+                p0[A][2] = 0.f;
+                pm[A][0] = x > 0 ? xs[par][A][x - 1] : 0.f;
+                pm[A][1] = py[A];
+                pm[A][2] = 0.f;
+            }
+            float tb[NLMAX];
+            kb_point<2, NLMAX, NNMAX, IDENT>(a, e0, l0, p0, pm, fwd, bwd, tb);
+            store_label_adjoint<NLMAX>(a, g, b, uv, dacc, tb);
+#pragma unroll
+            for (int A = 0; A < NNMAX; ++A) {
+                if (A < a.nn) {
+                    sto(field_w<float>(g.pbar_out, b, a.nn * 2, A * 2, V), uv, out[A][0]);
+                    sto(field_w<float>(g.pbar_out, b, a.nn * 2, A * 2 + 1, V), uv, out[A][1]);
+                }
+                py[A] = out[A][1];
+            }
+            add_sbar<NNMAX>(a, g, b, uv, sacc, sb);
+        }
+    }
+}
+
 // ------------------------------------------------------ utilities --------
 
 __global__ __launch_bounds__(kBlock) void k_fill(float *p, size_t n, float val) {
@@ -456,6 +532,14 @@ bool adj_fused_supported(int nd, int nl, int nn, bool identity) {
     return false;
 }
 
+// PF_KERNEL_AUTO takes the fused reverse step where it runs as the row march
+// (2-D rows of up to 512 voxels): the differentiation batch's backward 9.35
+// against 9.92 ms with the two kernels.  The tile form (3-D, wider rows)
+// measured slower than the two kernels and is used only on request.
+bool adj_fused_preferred(int nd, int nx, int nl, int nn, bool identity) {
+    return nd == 2 && nx <= ROW_COLS && adj_fused_supported(nd, nl, nn, identity);
+}
+
 hipError_t launch_adj_flow(const StepArgs &a, const AdjArgs &g, bool ident, int nd, hipStream_t s) {
     const dim3 grid((unsigned)((a.V + kBlock - 1) / kBlock), (unsigned)a.B, 1);
     return adj_dispatch(nd, ident, a.nl, a.nn, [&]<int ND, int NL, int NN, bool ID>() {
@@ -474,6 +558,24 @@ hipError_t launch_adj_label(const StepArgs &a, const AdjArgs &g, bool ident, int
 
 hipError_t launch_adj_fused(const StepArgs &a, const AdjArgs &g, bool ident, int nd, hipStream_t s) {
     if (!adj_fused_supported(nd, a.nl, a.nn, ident)) return hipErrorInvalidValue;
+    if (nd == 2 && a.nx <= ROW_COLS) {
+        // chunks of at least 4 rows; about 4096 wavefronts over the launch
+        // (16 per compute unit: on the 16 x 256^2 differentiation batch 8 and
+        // 16 rows per chunk measured 1-2% slower, 2 and 1 row 5-20% slower)
+        const long waves = (long)a.B * ((a.nx + 63) / 64);
+        const long want = (4096 + waves - 1) / waves;
+        const long max_chunks = (a.ny + 3) / 4;
+        const int n0 = (int)(want < max_chunks ? want : max_chunks);
+        const int cy = (a.ny + n0 - 1) / n0;
+        const int n_chunks = (a.ny + cy - 1) / cy;
+        const long blocks = (long)a.B * n_chunks;
+        if (blocks <= 0 || blocks > 0x7fffffffL) return hipErrorInvalidValue;
+        const unsigned threads = (unsigned)((a.nx + 63) / 64 * 64);
+        return adj_fused_dispatch(nd, ident, a.nl, [&]<int ND, int NL, int NN, bool ID>() {
+            k_adj_rows<NL, NN, ID><<<(unsigned)blocks, threads, 0, s>>>(a, g, cy, n_chunks);
+            return hipGetLastError();
+        });
+    }
     const FusedGeom geo = tile_geometry(a, RTX, RTY);
     if (geo.blocks <= 0 || geo.blocks > 0x7fffffffL) return hipErrorInvalidValue;
     return adj_fused_dispatch(nd, ident, a.nl, [&]<int ND, int NL, int NN, bool ID>() {

@@ -709,12 +709,14 @@ int run_backward(Prob &p, const pf_params *P, const float *grad_ell, float *grad
     const bool s_scalar = p.s_mode == PF_S_NODE_SCALAR;
     float *sbar = s_scalar ? reinterpret_cast<float *>(ws + L.sbar) : grad_S;
     const size_t n_sbar = (size_t)p.g.batch * (p.s_mode == PF_S_SHARED_FIELD ? 1 : p.nn) * V;
-    // AUTO: the two-kernel reverse step, measured faster on MI355X (the
-    // fused one holds one tile per compute unit at its register count)
+    // AUTO: the fused reverse step where it marches 2-D rows, the two-kernel
+    // step otherwise (measured faster on MI355X than the tile form, which
+    // holds one tile per compute unit at its register count)
     if (P->kernel == PF_KERNEL_FUSED2)
         return fail(PF_EUNSUPPORTED, "no two-iteration reverse kernel");
     if (P->kernel == PF_KERNEL_LDS) return fail(PF_EUNSUPPORTED, "no LDS-resident reverse kernel");
-    const bool fused = P->kernel == PF_KERNEL_FUSED;
+    const bool fused = P->kernel == PF_KERNEL_FUSED ||
+                       (P->kernel == PF_KERNEL_AUTO && adj_fused_preferred(nd, p.g.nx, p.nl, p.nn, p.ident));
     if (fused && !adj_fused_supported(nd, p.nl, p.nn, p.ident))
         return fail(PF_EUNSUPPORTED, "fused reverse kernel unavailable for this problem");
 

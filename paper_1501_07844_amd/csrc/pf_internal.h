@@ -165,6 +165,7 @@ hipError_t launch_adj_flow(const StepArgs &a, const AdjArgs &g, bool ident, int 
 hipError_t launch_adj_label(const StepArgs &a, const AdjArgs &g, bool ident, int nd, hipStream_t s);
 hipError_t launch_adj_fused(const StepArgs &a, const AdjArgs &g, bool ident, int nd, hipStream_t s);
 bool adj_fused_supported(int nd, int nl, int nn, bool identity);
+bool adj_fused_preferred(int nd, int nx, int nl, int nn, bool identity);
 hipError_t launch_fill(float *p, size_t n, float val, hipStream_t s);
 hipError_t launch_copy_f(const float *a, float *b, size_t n, hipStream_t s);
 // out[A] = sum over problems and voxels of sbar[B][nn][V] (fp64 accumulation)

@@ -298,6 +298,7 @@ def reverse_cases():
         ("tree3d scalar K7 k3", synth.random_problem(15, (3, 4, 5), 3, tree, s_mode="node_scalar", c=4.0, tau=0.0625, kind="hmf"), 7, 3),
         ("dag2d nl4 scalar K7 k3", synth.random_problem(17, (1, 19, 70), 2, small, s_mode="node_scalar", c=4.0, tau=0.0625), 7, 3),
         ("potts3d nl3 chunks K4 k2", synth.random_potts(18, (33, 10, 67), 3, 3, s_mode="node_field", c=1.0, tau=0.125), 4, 2),
+        ("potts2d nl3 rows K5 k2", synth.random_potts(19, (1, 23, 130), 2, 3, s_mode="node_field", c=1.0, tau=0.125), 5, 2),
     ]
 
 

@@ -245,7 +245,20 @@ hipError_t launch_adj_label(const StepArgs &a, const AdjArgs &g, bool ident, int
 hipError_t launch_adj_fused(const StepArgs &a, const AdjArgs &g, bool ident, int nd, hipStream_t) {
     if (!adj_fused_supported(nd, a.nl, a.nn, ident)) return 1;
     const FusedGeom geo = tile_geometry(a, RTX, RTY);
+    // 2-D rows of up to ROW_COLS voxels: the row march, same chunking as the library
+    const bool rows = nd == 2 && a.nx <= ROW_COLS;
+    const long waves = (long)a.B * ((a.nx + 63) / 64);
+    const long want = (4096 + waves - 1) / waves, max_chunks = (a.ny + 3) / 4;
+    const int n0 = (int)(want < max_chunks ? want : max_chunks);
+    const int cy = (a.ny + n0 - 1) / n0, n_chunks = (a.ny + cy - 1) / cy;
     auto f = [&]<int ND, int NL, int NN, bool ID>() {
+        if constexpr (ND == 2) {
+            if (rows) {
+                run_grid(dim3((unsigned)(a.B * n_chunks)), (unsigned)((a.nx + 63) / 64 * 64), true,
+                         [&] { k_adj_rows<NL, NN, ID>(a, g, cy, n_chunks); });
+                return 0;
+            }
+        }
         run_grid(dim3((unsigned)geo.blocks), RTHREADS, true, [&] { k_adj_fused<ND, NL, NN, ID>(a, g, geo); });
         return 0;
     };

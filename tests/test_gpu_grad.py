@@ -86,6 +86,8 @@ def _cases():
                                                          c=1.0, tau=0.125), 4, 2),
         "potts2d_nl8_shared": (synth.random_potts(21, (1, 17, 130), 2, 8, s_mode="shared_field",
                                                   c=2.0, tau=0.125), 5, 2),
+        "potts2d_wide_rows": (synth.random_potts(22, (1, 9, 530), 2, 3, s_mode="node_field",
+                                                 c=1.0, tau=0.125), 4, 2),
     }
 
 
@@ -104,14 +106,18 @@ def test_gradient_matches_oracle(name):
     assert eD <= G_RTOL and eS <= G_RTOL
 
 
+# 2-D rows of up to 512 voxels take the row march, wider ones (potts2d_wide_rows)
+# and 3-D problems the tile with halo wavefronts
 FUSED_BWD = ["potts2d_shared_B2", "potts3d_scalar", "potts2d_nodefield_nl5",
-             "dag2d_small_scalar", "potts3d_chunked_nodefield", "potts2d_nl8_shared"]
+             "dag2d_small_scalar", "potts3d_chunked_nodefield", "potts2d_nl8_shared",
+             "potts2d_wide_rows"]
 
 
 @pytest.mark.parametrize("name", FUSED_BWD)
 def test_fused_reverse_equals_two_kernel_bitwise(name):
-    """The fused reverse step (tile + halo wavefront, ping-pong adjoints)
-    evaluates the same per-point expressions as the two-kernel step."""
+    """The fused reverse step (row march in 2-D, tile + halo wavefronts
+    otherwise; ping-pong adjoints) evaluates the same per-point expressions
+    as the two-kernel step."""
     p, iters, ckpt = CASES[name]
     w = np.random.default_rng(3).standard_normal(p.D.shape).astype(np.float32)
     a = _gpu_grad(p, iters, ckpt, w, backward_kernel="two_pass")
