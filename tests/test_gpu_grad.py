@@ -88,6 +88,8 @@ def _cases():
                                                   c=2.0, tau=0.125), 5, 2),
         "potts2d_wide_rows": (synth.random_potts(22, (1, 9, 530), 2, 3, s_mode="node_field",
                                                  c=1.0, tau=0.125), 4, 2),
+        "potts2d_rows_512": (synth.random_potts(23, (1, 7, 512), 2, 4, batch=2, s_mode="shared_field",
+                                                c=2.0, tau=0.125), 4, 3),
     }
 
 
@@ -106,11 +108,12 @@ def test_gradient_matches_oracle(name):
     assert eD <= G_RTOL and eS <= G_RTOL
 
 
-# 2-D rows of up to 512 voxels take the row march, wider ones (potts2d_wide_rows)
-# and 3-D problems the tile with halo wavefronts
+# 2-D rows of up to 512 voxels take the row march (potts2d_rows_512: the
+# widest), wider ones (potts2d_wide_rows) and 3-D problems the tile with halo
+# wavefronts
 FUSED_BWD = ["potts2d_shared_B2", "potts3d_scalar", "potts2d_nodefield_nl5",
              "dag2d_small_scalar", "potts3d_chunked_nodefield", "potts2d_nl8_shared",
-             "potts2d_wide_rows"]
+             "potts2d_wide_rows", "potts2d_rows_512"]
 
 
 @pytest.mark.parametrize("name", FUSED_BWD)
