@@ -192,7 +192,7 @@ def copy_leg(dev) -> dict:
             "GBs": round(2 * COPY_BYTES / (ms * 1e-3) / 1e9, 1)}
 
 
-def adjoint_leg(dev, reps: int = 3) -> dict:
+def adjoint_leg(dev, reps: int = 5) -> dict:
     """Cost of the differentiable solve on its own workload: 16 Potts problems
     of 256 x 256, 5 labels, 100 unrolled iterations, checkpoint every 10,
     cross-entropy loss against the ground-truth labels.  Times (HIP events on

@@ -393,9 +393,18 @@ bool flow_label_preferred(int nd, int nl, int nn, bool identity, int storage, bo
     return storage == PF_FP32 && nn > 8;
 }
 
-// About four blocks per compute unit over the pass, chunks of at least 16
-// planes (each chunk recomputes one flow plane below it).
-FusedGeom flow_label_geometry(const StepArgs &a) { return tile_geometry(a, GX, GY, 1024); }
+// z chunks of about 32 planes (each chunk recomputes one flow plane below
+// it), but at least one block per compute unit, and chunks of at least 16
+// planes.  Measured per iteration against chunk counts from 1 to 16: DAGMF
+// 256x512x512 (512 tiles, 8 chunks) fp32 8.69 ms (9.30 with 1 or 2 chunks,
+// 9.00 with 4), bf16 4.99-5.00 (5.00-5.02 with 1-4, 5.09 with 16); HMF
+// 128x256x256 (128 tiles, 4 chunks) fp32 0.724 ms, bf16 0.466 (2 chunks:
+// 0.71, 0.454; 8: 0.753, 0.473; 1 chunk leaves half the compute units idle).
+FusedGeom flow_label_geometry(const StepArgs &a) {
+    const long tiles = (long)((a.nx + GX - 1) / GX) * ((a.ny + GY - 1) / GY) * a.B;
+    const long by_depth = tiles * ((a.nz + 31) / 32);
+    return tile_geometry(a, GX, GY, by_depth > 256 ? by_depth : 256);
+}
 
 hipError_t launch_flow_label(const StepArgs &a, int storage, bool tail, hipStream_t s) {
     if (!flow_label_supported(3, a.nl, a.nn, false) || a.nz < 1) return hipErrorInvalidValue;
