@@ -74,13 +74,13 @@ typedef enum {
                                 8 flows up to 2^21 voxel-fields (voxels x problems
                                 x (n_leaf + n_node)); for 3-D Potts FUSED2 up to 8
                                 labels (every storage type), beyond that FUSED with
-                                fp32 state; FUSED for 3-D label graphs (DAGMF, HMF,
-                                Ishikawa chain) of 9 to 16 flows and at most 16
-                                leaves with fp32 state, and in every storage type
-                                for 3-D graphs whose end-labels are the last nodes,
-                                under 4 internal nodes with 4, 8, 12 or 16 leaves,
-                                under 8 with 8 or 12, or under 3 with 8; two-pass
-                                otherwise */
+                                fp32 state; FUSED for 3-D label graphs (DAGMF, HMF)
+                                of at most 16 flows and 16 leaves with fp32 state,
+                                and in every storage type for 3-D graphs whose
+                                end-labels are the last nodes, under 4 internal
+                                nodes with 4, 8, 12 or 16 leaves, under 8 with 8 or
+                                12, or under 3 with 8; two-pass otherwise (the 3-D
+                                Ishikawa chain always) */
     PF_KERNEL_TWO_PASS = 1,  /* label pass then flow pass, state updated in place */
     PF_KERNEL_FUSED = 2,     /* one pass per iteration, state ping-ponged (at most 16
                                 leaves and 16 flows; 3-D label graphs run the flow
@@ -173,9 +173,10 @@ size_t pf_workspace_bytes(const pf_grid *grid, int32_t n_leaf, int32_t n_node,
 
 /* The kernel PF_KERNEL_AUTO runs for an unrecorded solve of this problem:
  * identity != 0 for the Potts model, 0 for a label graph (DAGMF, HMF, and the
- * Ishikawa chain, whose AUTO follows the same rule; a graph is taken to
- * number its end-labels last, as every graph whose leaves have the highest
- * node ids does); storage is a pf_storage.  Host only, no device work.  Returns PF_KERNEL_TWO_PASS, PF_KERNEL_FUSED,
+ * Ishikawa chain, whose AUTO follows the same rule and which is told from the
+ * others by having fewer flows than labels, n_node = n_leaf - 1; a graph is
+ * taken to number its end-labels last, as every graph whose leaves have the
+ * highest node ids does); storage is a pf_storage.  Host only, no device work.  Returns PF_KERNEL_TWO_PASS, PF_KERNEL_FUSED,
  * PF_KERNEL_FUSED2 or PF_KERNEL_LDS, or -1 for arguments no solver accepts. */
 int32_t pf_auto_kernel(const pf_grid *grid, int32_t n_leaf, int32_t n_node, int32_t identity,
                        int32_t storage);
@@ -212,8 +213,7 @@ int solve_hmf(const pf_grid *grid, const pf_graph *graph, const float *D, const 
  * L_i driven by U_i = sum_{j>=i} u_j.  D: device float[B][N+1][Z][Y][X];
  * S per s_mode with n_node = N.  Supports PF_KERNEL_TWO_PASS, PF_KERNEL_LDS,
  * PF_KERNEL_FUSED on 3-D grids, and AUTO (the rule of pf_auto_kernel with
- * identity = 0: LDS for small 2-D problems, FUSED on 3-D grids, else
- * two-pass). */
+ * identity = 0: LDS for small 2-D problems, else two-pass). */
 int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
                    int32_t s_mode, const pf_params *params, pf_result *result, void *stream);
 

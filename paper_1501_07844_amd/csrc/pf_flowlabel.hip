@@ -374,23 +374,25 @@ static bool flow_label_tail_exact(int nl, int nn) {
 }
 
 // PF_KERNEL_AUTO takes this pass where it measured faster than the two-pass
-// kernels on MI355X: float32 state with more than 8 flows (per iteration:
-// DAGMF 256x512x512 9.29 against 10.6-11.5 ms, HMF 128x256x256 0.796 against
-// 0.847 ms; the 7-flow Ishikawa chain 0.62 against 0.62 ms), and every
-// storage type for the EXACT forms (DAGMF bf16 5.00 against 5.60 ms, fp16
-// 5.00 against 5.73; the HMF tree bf16 0.452 against 0.483 ms, fp32 0.747
-// against 0.836; random DAGs of 4/8, 8/8, 4/12 and 4/4 internal nodes /
-// leaves at 128x256x256, bf16: 1.09, 1.04, 1.09 and 1.05x faster, fp32:
-// 1.12-1.15x).  Otherwise, with 16-bit state, the two-pass kernels stay
-// ahead (the HMF tree in a non-exact build: 0.564 against 0.490 ms): this
-// pass issues more instructions than the two passes (halo recomputation,
-// and the slot and label masks of graphs that do not fill the build) at one
-// block per compute unit, while the two passes are bound by memory
-// bandwidth.
+// kernels on MI355X (per iteration at 128x256x256 unless stated, z chunks
+// of 32 planes): every label graph with float32 state (DAGMF 256x512x512
+// 8.68 against 10.6-11.5 ms, the HMF tree 0.720 against 0.836; random DAGs
+// and trees of 3 to 16 flows 1.035-1.24x faster), and every storage type for
+// the EXACT forms (DAGMF bf16 4.97-4.99 against 5.60 ms, fp16 4.97 against
+// 5.73; the HMF tree bf16 0.436 against 0.483; random DAGs of 4/8, 8/8, 4/12
+// and 4/4 internal nodes / leaves, bf16: 1.07-1.20x).  Otherwise, with
+// 16-bit state, the two-pass kernels stay ahead (non-exact DAGs of 2/6 and
+// 6/10: 0.84x and 0.79x): this pass issues more instructions than the two
+// passes (halo recomputation, and the slot and label masks of graphs that
+// do not fill the build) at one block per compute unit, while the two
+// passes are bound by memory bandwidth.  The Ishikawa chain, the only graph
+// with fewer flows than labels, stays on the two-pass kernels in every
+// storage type: with float32 state this pass measured 0.88-1.13x (3, 5, 6,
+// 8 and 10 labels: 1.13, 0.88, 0.96, 1.05, 0.88).
 bool flow_label_preferred(int nd, int nl, int nn, bool identity, int storage, bool tail) {
     if (!flow_label_supported(nd, nl, nn, identity)) return false;
     if (tail && flow_label_tail_exact(nl, nn) && flow_label_tail_supported(nl, nn, storage)) return true;
-    return storage == PF_FP32 && nn > 8;
+    return storage == PF_FP32 && nn >= nl;
 }
 
 // z chunks of about 32 planes (each chunk recomputes one flow plane below

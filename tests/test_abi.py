@@ -102,7 +102,11 @@ def test_auto_kernel_choice():
     assert pf.auto_kernel((1, 16, 16, 16), 7, 10, 3, "bf16", identity=False) == "two_pass"
     assert pf.auto_kernel((1, 16, 16, 16), 10, 14, 3, "bf16", identity=False) == "two_pass"
     assert pf.auto_kernel((1, 16, 16, 16), 16, 16, 3, "fp16", identity=False) == "two_pass"
-    assert pf.auto_kernel((1, 16, 16, 16), 8, 7, 3, identity=False) == "two_pass"   # 7 flows
+    assert pf.auto_kernel((1, 16, 16, 16), 8, 7, 3, identity=False) == "two_pass"   # Ishikawa chain
+    assert pf.auto_kernel((1, 16, 16, 16), 10, 9, 3, identity=False) == "two_pass"  # Ishikawa chain
+    assert pf.auto_kernel((1, 16, 16, 16), 4, 6, 3, identity=False) == "fused"      # fp32 DAG, 6 flows
+    assert pf.auto_kernel((1, 16, 16, 16), 2, 3, 3, identity=False) == "fused"
+    assert pf.auto_kernel((1, 16, 16, 16), 4, 6, 3, "bf16", identity=False) == "two_pass"
     assert pf.auto_kernel((1, 16, 16, 16), 16, 30, 3, identity=False) == "two_pass"  # 30 flows
     assert pf.auto_kernel((1, 1, 64, 64), 8, 11, 2, identity=False) == "two_pass"   # 2-D, 11 flows
     assert pf.auto_kernel((1, 1, 64, 64), 5, 8, 2, identity=False) == "lds"         # 2-D, 8 flows
