@@ -79,8 +79,10 @@ typedef enum {
                                 and in every storage type for 3-D graphs whose
                                 end-labels are the last nodes, under 4 internal
                                 nodes with 4, 8, 12 or 16 leaves, under 8 with 8 or
-                                12, or under 3 with 8; two-pass otherwise (the 3-D
-                                Ishikawa chain always) */
+                                12, or under 3 with 8; FUSED for the 3-D Ishikawa
+                                chain with fp32 state unless it has 5, 9 or 13
+                                labels, and with 16-bit state up to 4 labels;
+                                two-pass otherwise */
     PF_KERNEL_TWO_PASS = 1,  /* label pass then flow pass, state updated in place */
     PF_KERNEL_FUSED = 2,     /* one pass per iteration, state ping-ponged (at most 16
                                 leaves and 16 flows; 3-D label graphs run the flow
@@ -213,7 +215,8 @@ int solve_hmf(const pf_grid *grid, const pf_graph *graph, const float *D, const 
  * L_i driven by U_i = sum_{j>=i} u_j.  D: device float[B][N+1][Z][Y][X];
  * S per s_mode with n_node = N.  Supports PF_KERNEL_TWO_PASS, PF_KERNEL_LDS,
  * PF_KERNEL_FUSED on 3-D grids, and AUTO (the rule of pf_auto_kernel with
- * identity = 0: LDS for small 2-D problems, else two-pass). */
+ * identity = 0: LDS for small 2-D problems, FUSED on 3-D grids where it
+ * measured faster, else two-pass). */
 int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const float *S,
                    int32_t s_mode, const pf_params *params, pf_result *result, void *stream);
 

@@ -161,7 +161,32 @@ __device__ __forceinline__ void fl_entropic_step(const StepArgs &a, const float 
 // voxel and the capacities; returns the new flows of every slot after a
 // round trip through the storage type (what a later load returns; 0 in a
 // slot past the graph) and stores them when `store`.
-template <int NLMAX, int NI, bool TAIL, bool EXACT, typename T>
+// The Ishikawa chain's path weights are fixed (Algorithm 3): flow j drives
+// every label after it, W[j][L] = 1 for L > j and 0 otherwise.  Builds for
+// the chain (CH) take them at compile time: grad U_j is the sum of the label
+// gradients above j and a flow's divergence adds to the excess of every
+// label above it.  These are grad_U's and add_excess's sums with the zero
+// terms left out, in the same order, so they give the same values (a term
+// fma(0, x, s) leaves a finite sum s unchanged up to the sign of a zero).
+// The gradients of padding labels (L >= nl) must be zero.
+template <int NLMAX>
+__device__ __forceinline__ void grad_U_chain(int A, const float (&gu)[NLMAX][3], float (&G)[3]) {
+    G[0] = G[1] = G[2] = 0.f;
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L)
+        if (L > A)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) G[k] = fmaf(1.f, gu[L][k], G[k]);
+}
+
+template <int NLMAX>
+__device__ __forceinline__ void add_excess_chain(float (&d)[NLMAX], int A, float dv) {
+#pragma unroll
+    for (int L = 0; L < NLMAX; ++L)
+        if (L > A) d[L] = fmaf(1.f, dv, d[L]);
+}
+
+template <int NLMAX, int NI, bool TAIL, bool EXACT, typename T, bool CH = false>
 __device__ __forceinline__ void flow_point(const StepArgs &a, int b, int x, int y, int z, bool store,
                                            float (&e0)[NLMAX],
                                            float (&pr)[Slots<NLMAX, NI, TAIL, EXACT>::NP][3]) {
@@ -203,6 +228,7 @@ __device__ __forceinline__ void flow_point(const StepArgs &a, int b, int x, int 
         const float u0 = __expf(e0[L]);
 #pragma unroll
         for (int k = 0; k < 3; ++k) gu[L][k] = h[k] ? __expf(en[L][k]) - u0 : 0.f;
+        if (CH && L >= a.nl) gu[L][0] = gu[L][1] = gu[L][2] = 0.f;
     }
     // slot pairs, stored as they are formed; with 16-bit state a slot pair
     // is a node pair (2P, 2P + 1) of one packed word (NI and ni are even)
@@ -218,7 +244,10 @@ __device__ __forceinline__ void flow_point(const StepArgs &a, int b, int x, int 
                     const int L = s + j - NI;
                     G[0] = gu[L][0], G[1] = gu[L][1], G[2] = gu[L][2];
                 } else {
-                    grad_U<3, NLMAX, false>(a, s + j, gu, G);
+                    if constexpr (CH)
+                        grad_U_chain<NLMAX>(s + j, gu, G);
+                    else
+                        grad_U<3, NLMAX, false>(a, s + j, gu, G);
                 }
                 flow_project<3>(a, qv[s + j], G, h, sv[s + j], p[j]);
             }
@@ -249,7 +278,7 @@ __device__ __forceinline__ void flow_point(const StepArgs &a, int b, int x, int 
     }
 }
 
-template <int NLMAX, int NI, bool TAIL, bool EXACT, typename T>
+template <int NLMAX, int NI, bool TAIL, bool EXACT, typename T, bool CH = false>
 __global__ __launch_bounds__(GTHREADS) void k_flow_label(StepArgs a, FusedGeom g) {
     using SL = Slots<NLMAX, NI, TAIL, EXACT>;
     constexpr int NS = SL::N;
@@ -289,7 +318,7 @@ __global__ __launch_bounds__(GTHREADS) void k_flow_label(StepArgs a, FusedGeom g
     for (int s = 0; s < NS; ++s) pzb[s] = 0.f;
     if (own && zs > 0) {
         float e0[NLMAX], pr[SL::NP][3];
-        flow_point<NLMAX, NI, TAIL, EXACT, T>(a, b, xa, ya, zs - 1, false, e0, pr);
+        flow_point<NLMAX, NI, TAIL, EXACT, T, CH>(a, b, xa, ya, zs - 1, false, e0, pr);
 #pragma unroll
         for (int s = 0; s < NS; ++s) pzb[s] = pr[s][2];
     }
@@ -298,7 +327,7 @@ __global__ __launch_bounds__(GTHREADS) void k_flow_label(StepArgs a, FusedGeom g
         float e0[NLMAX], pz[NS], dl[NLMAX];
         if (va) {
             float pr[SL::NP][3];
-            flow_point<NLMAX, NI, TAIL, EXACT, T>(a, b, xa, ya, z, own, e0, pr);
+            flow_point<NLMAX, NI, TAIL, EXACT, T, CH>(a, b, xa, ya, z, own, e0, pr);
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 lq[s][0][lr][lc] = pr[s][0];
@@ -334,7 +363,10 @@ __global__ __launch_bounds__(GTHREADS) void k_flow_label(StepArgs a, FusedGeom g
                 if (SL::tail(s)) {
                     dl[s - NI] += dv;
                 } else {
-                    add_excess<NLMAX, false>(a, dl, s, dv);
+                    if constexpr (CH)
+                        add_excess_chain<NLMAX>(dl, s, dv);
+                    else
+                        add_excess<NLMAX, false>(a, dl, s, dv);
                 }
             }
             fl_entropic_step<NLMAX, EXACT>(a, dl, e0);
@@ -386,13 +418,20 @@ static bool flow_label_tail_exact(int nl, int nn) {
 // passes (halo recomputation, and the slot and label masks of graphs that
 // do not fill the build) at one block per compute unit, while the two
 // passes are bound by memory bandwidth.  The Ishikawa chain, the only graph
-// with fewer flows than labels, stays on the two-pass kernels in every
-// storage type: with float32 state this pass measured 0.88-1.13x (3, 5, 6,
-// 8 and 10 labels: 1.13, 0.88, 0.96, 1.05, 0.88).
+// with fewer flows than labels, runs builds of 4, 8, 12 or 16 labels with its
+// weights fixed; it takes this pass with float32 state where it leaves at
+// most 2 padding labels in its build (3, 4, 6, 8, 10, 12 and 16 labels:
+// 1.46, 1.24, 1.05, 1.11, 1.14, 1.15 and 1.11x; 5 labels: 0.95x) and with
+// 16-bit state up to 4 labels (bf16 1.31 and 1.07x; 8, 12 and 16 labels
+// 1.00-1.02x, 5, 6 and 10 labels 0.78-0.95x).
 bool flow_label_preferred(int nd, int nl, int nn, bool identity, int storage, bool tail) {
     if (!flow_label_supported(nd, nl, nn, identity)) return false;
+    if (nn == nl - 1) {
+        const int build = nl <= 4 ? 4 : nl <= 8 ? 8 : nl <= 12 ? 12 : 16;
+        return storage == PF_FP32 ? build - nl <= 2 : nl <= 4;
+    }
     if (tail && flow_label_tail_exact(nl, nn) && flow_label_tail_supported(nl, nn, storage)) return true;
-    return storage == PF_FP32 && nn >= nl;
+    return storage == PF_FP32;
 }
 
 // z chunks of about 32 planes (each chunk recomputes one flow plane below
@@ -425,7 +464,19 @@ hipError_t launch_flow_label(const StepArgs &a, int storage, bool tail, hipStrea
             return hipErrorInvalidValue;
         return hipGetLastError();
     };
+    // the Ishikawa chain, the only graph with fewer flows than labels, runs
+    // the builds with its path weights fixed
+    auto chain = [&]<int NL, typename T>() {
+        k_flow_label<NL, NL, false, false, T, true><<<(unsigned)g.blocks, GTHREADS, 0, s>>>(a, g);
+        return hipGetLastError();
+    };
     auto by = [&]<typename T>() -> hipError_t {
+        if (a.nn == a.nl - 1) {
+            if (a.nl <= 4) return chain.template operator()<4, T>();
+            if (a.nl <= 8) return chain.template operator()<8, T>();
+            if (a.nl <= 12) return chain.template operator()<12, T>();
+            return chain.template operator()<16, T>();
+        }
         if (tail) {
             if (ni == 3 && a.nl == 8) return go.template operator()<8, 3, true, T>();
             if (ni <= 4 && a.nl <= 4) return go.template operator()<4, 4, true, T>();

@@ -179,6 +179,11 @@ def flow_label_cases():
         ("hmf3d nl8 nn11 shared gap2", synth.random_problem(5, (20, 13, 35), 3, tree, s_mode="shared_field"), 5, 2),
         ("dagmf3d nl12 nn16", synth.dagmf_blobs(shape=(18, 14, 66)), 3, 0),
         ("ishikawa3d 8 levels", synth.ishikawa_levels(shape=(17, 7, 35), n_levels=7), 3, 0),
+        # chains in builds with padding labels, and the largest chain build
+        ("ishikawa3d 3 levels", synth.ishikawa_levels(shape=(18, 6, 67), n_levels=2), 3, 2),
+        ("ishikawa3d 5 levels", synth.ishikawa_levels(shape=(9, 11, 30), n_levels=4), 3, 0),
+        ("ishikawa3d 12 levels", synth.ishikawa_levels(shape=(5, 9, 20), n_levels=11), 2, 0),
+        ("ishikawa3d 16 levels", synth.ishikawa_levels(shape=(4, 5, 66), n_levels=15), 2, 0),
         ("dag3d nl16 nn16", synth.random_problem(6, (9, 8, 34), 3, big, s_mode="node_scalar"), 2, 0),
         ("tree3d nl2 nn3 thin", synth.random_problem(7, (3, 2, 40), 3, tiny, s_mode="node_field"), 3, 0),
         # graphs filling every slot of a tail build (the EXACT forms)

@@ -171,7 +171,17 @@ hipError_t launch_flow_label(const StepArgs &a, int st, bool tail, hipStream_t) 
             return 1;
         return 0;
     };
+    auto chain = [&]<int NL, typename T>() {
+        run_grid(dim3((unsigned)g.blocks), GTHREADS, true, [&] { k_flow_label<NL, NL, false, false, T, true>(a, g); });
+        return 0;
+    };
     auto by = [&]<typename T>() -> hipError_t {
+        if (a.nn == a.nl - 1) {
+            if (a.nl <= 4) return chain.template operator()<4, T>();
+            if (a.nl <= 8) return chain.template operator()<8, T>();
+            if (a.nl <= 12) return chain.template operator()<12, T>();
+            return chain.template operator()<16, T>();
+        }
         if (tail) {
             if (ni == 3 && a.nl == 8) return go.template operator()<8, 3, true, T>();
             if (ni <= 4 && a.nl <= 4) return go.template operator()<4, 4, true, T>();

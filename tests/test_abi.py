@@ -102,8 +102,14 @@ def test_auto_kernel_choice():
     assert pf.auto_kernel((1, 16, 16, 16), 7, 10, 3, "bf16", identity=False) == "two_pass"
     assert pf.auto_kernel((1, 16, 16, 16), 10, 14, 3, "bf16", identity=False) == "two_pass"
     assert pf.auto_kernel((1, 16, 16, 16), 16, 16, 3, "fp16", identity=False) == "two_pass"
-    assert pf.auto_kernel((1, 16, 16, 16), 8, 7, 3, identity=False) == "two_pass"   # Ishikawa chain
-    assert pf.auto_kernel((1, 16, 16, 16), 10, 9, 3, identity=False) == "two_pass"  # Ishikawa chain
+    # Ishikawa chains (n_node = n_leaf - 1): fp32 unless 3 padding labels in the build
+    assert pf.auto_kernel((1, 16, 16, 16), 8, 7, 3, identity=False) == "fused"
+    assert pf.auto_kernel((1, 16, 16, 16), 10, 9, 3, identity=False) == "fused"
+    assert pf.auto_kernel((1, 16, 16, 16), 5, 4, 3, identity=False) == "two_pass"
+    assert pf.auto_kernel((1, 16, 16, 16), 13, 12, 3, identity=False) == "two_pass"
+    assert pf.auto_kernel((1, 16, 16, 16), 8, 7, 3, "bf16", identity=False) == "two_pass"
+    assert pf.auto_kernel((1, 16, 16, 16), 3, 2, 3, "fp16", identity=False) == "fused"
+    assert pf.auto_kernel((1, 1, 64, 64), 8, 7, 2, identity=False) == "lds"
     assert pf.auto_kernel((1, 16, 16, 16), 4, 6, 3, identity=False) == "fused"      # fp32 DAG, 6 flows
     assert pf.auto_kernel((1, 16, 16, 16), 2, 3, 3, identity=False) == "fused"
     assert pf.auto_kernel((1, 16, 16, 16), 4, 6, 3, "bf16", identity=False) == "two_pass"

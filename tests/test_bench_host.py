@@ -48,7 +48,8 @@ def test_kernel_choice_per_workload():
         assert bench._kernel_choice(pf, synth.dagmf_blobs(shape=(4, 5, 6)), st, "auto") == "fused"
     assert bench._kernel_name(synth.dagmf_blobs(shape=(4, 5, 6)), "fused") == "k_flow_label"
     q = synth.ishikawa_levels(shape=(4, 5, 6), n_levels=7)
-    assert bench._kernel_choice(pf, q, "fp32", "auto") == "two_pass"     # 7 flows
+    assert bench._kernel_choice(pf, q, "fp32", "auto") == "fused"        # chain build
+    assert bench._kernel_choice(pf, q, "bf16", "auto") == "two_pass"
     assert bench._kernel_name(q, "fused") == "k_flow_label"
     assert bench._kernel_name(p, "fused") == "k_fused"
     # a small 2-D chain of one problem runs in LDS tiles with ghost zones

@@ -218,6 +218,11 @@ FLOW_LABEL_CASES = {
     "hmf_ellipsoids_20x36x44": (lambda: WORKLOADS["hmf_ellipsoids_20x36x44"](), 0),
     "dagmf_blobs_18x30x38_gap7": (lambda: WORKLOADS["dagmf_blobs_18x30x38"](), 7),
     "ishikawa_levels_20x36x44_n7": (lambda: WORKLOADS["ishikawa_levels_20x36x44_n7"](), 0),
+    # chains in the chain builds of 4, 8, 12 and 16 labels, with padding labels
+    "ishikawa_3_labels_gap5": (lambda: synth.ishikawa_levels(shape=(21, 13, 70), n_levels=2), 5),
+    "ishikawa_5_labels": (lambda: synth.ishikawa_levels(shape=(19, 17, 40), n_levels=4), 0),
+    "ishikawa_12_labels": (lambda: synth.ishikawa_levels(shape=(7, 12, 67), n_levels=11), 0),
+    "ishikawa_16_labels": (lambda: synth.ishikawa_levels(shape=(6, 9, 40), n_levels=15), 0),
     "dag_nl16_nn16_B2_field": (lambda: synth.random_problem(
         37, (9, 14, 70), 3, synth.random_dag(np.random.default_rng(37), 0, 16), batch=2,
         s_mode="node_field"), 0),
