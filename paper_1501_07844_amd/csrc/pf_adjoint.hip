@@ -513,12 +513,14 @@ hipError_t adj_dispatch(int nd, bool ident, int nl, int nn, F &&f) {
 // The fused reverse kernel keeps a point's whole adjoint state in registers;
 // it is built for the buckets that fit in the register budget of a
 // 640-thread block without spilling: Potts up to 8
-// labels in 2-D and 4 in 3-D, label graphs up to 4 leaves / 8 flows in 2-D.
+// labels in 2-D (builds of 4, 6 and 8) and 4 in 3-D, label graphs up to 4
+// leaves / 8 flows in 2-D.
 template <typename F>
 hipError_t adj_fused_dispatch(int nd, bool ident, int nl, F &&f) {
     if (nd == 2) {
         if (!ident) return f.template operator()<2, 4, 8, false>();
         if (nl <= 4) return f.template operator()<2, 4, 4, true>();
+        if (nl <= 6) return f.template operator()<2, 6, 6, true>();
         return f.template operator()<2, 8, 8, true>();
     }
     return f.template operator()<3, 4, 4, true>();
@@ -533,8 +535,8 @@ bool adj_fused_supported(int nd, int nl, int nn, bool identity) {
 }
 
 // PF_KERNEL_AUTO takes the fused reverse step where it runs as the row march
-// (2-D rows of up to 512 voxels): the differentiation batch's backward 9.35
-// against 9.92 ms with the two kernels.  The tile form (3-D, wider rows)
+// (2-D rows of up to 512 voxels): the differentiation batch's backward 9.07
+// (6-label build) against 10.0 ms with the two kernels.  The tile form (3-D, wider rows)
 // measured slower than the two kernels and is used only on request.
 bool adj_fused_preferred(int nd, int nx, int nl, int nn, bool identity) {
     return nd == 2 && nx <= ROW_COLS && adj_fused_supported(nd, nl, nn, identity);

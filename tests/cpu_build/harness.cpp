@@ -275,6 +275,7 @@ hipError_t launch_adj_fused(const StepArgs &a, const AdjArgs &g, bool ident, int
     if (nd == 2) {
         if (!ident) return f.template operator()<2, 4, 8, false>();
         if (a.nl <= 4) return f.template operator()<2, 4, 4, true>();
+        if (a.nl <= 6) return f.template operator()<2, 6, 6, true>();
         return f.template operator()<2, 8, 8, true>();
     }
     return f.template operator()<3, 4, 4, true>();
