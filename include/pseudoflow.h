@@ -229,7 +229,9 @@ int solve_ishikawa(const pf_grid *grid, int32_t n_labels, const float *D, const 
  * solver state lives in a static device array of PF_STATIC_SCRATCH_BYTES
  * (128 MiB) that every GPU the library runs on holds until the process ends;
  * a problem whose state and buffers need more (the workspace layout of the
- * kernel the call runs) returns PF_ENOMEM before any device work.  The call allocates nothing: no hipMalloc, no
+ * kernel the call runs) returns PF_ENOMEM before any device work.  Under
+ * PF_KERNEL_AUTO the call takes the two-pass kernels (one copy of the state)
+ * where the faster kernel's layout (two copies) would not fit.  The call allocates nothing: no hipMalloc, no
  * hipFree, no HIP events.  It runs on the current device, and a non-NULL
  * stream must belong to it (else PF_EINVAL).  Every call on a GPU shares that
  * GPU's array and it keeps the last call's contents: the solver initialises

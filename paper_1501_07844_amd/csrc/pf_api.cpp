@@ -326,22 +326,27 @@ int run(Prob &p, const pf_params *P, pf_result *R, hipStream_t stream, bool stat
                     P->kernel == PF_KERNEL_LDS))
         return fail(PF_EUNSUPPORTED, "a recorded solve uses the two-pass kernels");
     const long V = (long)p.g.nx * p.g.ny * p.g.nz;
+    // AUTO may take a kernel that ping-pongs the state (tiles, fused passes)
+    // unless, on the static scratch, that layout would not fit where the
+    // single-state layout of the two-pass kernels does
+    const bool auto_pp = P->kernel == PF_KERNEL_AUTO &&
+                         !(static_ws && make_layout(p.g, p.nl, p.nn, P->storage, true).total >
+                                            (size_t)PF_STATIC_SCRATCH_BYTES);
     // PF_KERNEL_LDS: whole problems per block for batches that fill the GPU
     // (and fit), tiles with ghost zones otherwise
     const bool lds_kind = !P->tape && (P->kernel == PF_KERNEL_LDS ||
                           (P->kernel == PF_KERNEL_AUTO &&
                            (lds_preferred(p.g.ndim, p.nl, p.nn, V, p.g.batch) ||
-                            tile_preferred(p.g.ndim, p.nl, p.nn, V, p.g.batch))));
+                            (auto_pp && tile_preferred(p.g.ndim, p.nl, p.nn, V, p.g.batch)))));
     const bool want_lds = lds_kind && lds_preferred(p.g.ndim, p.nl, p.nn, V, p.g.batch);
     const bool want_tile = lds_kind && !want_lds;
     if (want_tile && !tile_supported(p.g.ndim, p.nl, p.nn))
         return fail(PF_EUNSUPPORTED, "LDS-resident iterations serve 2-D problems of up to 8 labels "
                                      "and 16 flows");
     const bool want_fused2 = !P->tape && !lds_kind && (P->kernel == PF_KERNEL_FUSED2 ||
-                             (P->kernel == PF_KERNEL_AUTO &&
-                              fused2_preferred(p.g.ndim, p.nl, p.nn, p.ident, P->storage)));
+                             (auto_pp && fused2_preferred(p.g.ndim, p.nl, p.nn, p.ident, P->storage)));
     const bool want_fused = want_fused2 || (!P->tape && !lds_kind && (P->kernel == PF_KERNEL_FUSED ||
-                            (P->kernel == PF_KERNEL_AUTO &&
+                            (auto_pp &&
                              any_fused_preferred(p.g.ndim, p.nl, p.nn, p.ident, P->storage, p.tail))));
     if (P->kernel == PF_KERNEL_FUSED && !fused_supported(p.g.ndim, p.nl, p.nn, p.ident))
         return fail(PF_EUNSUPPORTED, "fused kernel unavailable for this problem");

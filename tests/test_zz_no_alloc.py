@@ -2,7 +2,8 @@
 allocate device memory) against solve_dagmf with a caller workspace: the same
 kernels run on the same inputs, so the results agree bit for bit.  Two calls
 in a row with the second smaller, warm starts from the static scratch, the
-LDS-resident kernels on a batch of 2-D problems and in tiles on one, the
+LDS-resident kernels on a batch of 2-D problems and in tiles on one, AUTO's
+fall-back to the single-state kernels where two state copies do not fit, the
 size limit and the argument checks, all through the C ABI."""
 import ctypes as C
 
@@ -75,6 +76,25 @@ def test_static_scratch_warm_start_and_lds_batch():
     pf.solve_dagmf_static(Dt, St, t.graph, iters=13, **kt)
     rest = pf.solve_dagmf_static(Dt, St, t.graph, iters=8, warm_start=True, **kt)
     assert torch.equal(full.u, rest.u) and torch.equal(full.q, rest.q)
+
+
+def test_static_scratch_auto_takes_one_state_copy_where_two_do_not_fit():
+    # 32 x 112 x 112 voxels of the DAGMF workload's graph in fp32: the
+    # flow-then-label pass (two copies of the state) needs 184 MiB, the
+    # two-pass kernels 92 MiB; AUTO on the static scratch runs the latter
+    p = synth.dagmf_blobs(shape=(32, 112, 112), iters=10)
+    lim = 128 << 20
+    assert pf.workspace_bytes(p.shape, 12, 16, 3, kernel="two_pass") <= lim
+    assert pf.workspace_bytes(p.shape, 12, 16, 3, kernel="fused") > lim
+    D, S = device_inputs(p)
+    kw = dict(c=p.c, tau=p.tau, iters=10, ndim=3, s_mode=p.s_mode, return_q=True)
+    print(f"[static] {p.shape}: AUTO on the static scratch", flush=True)
+    a = pf.solve_dagmf(D, S, p.graph, kernel="two_pass", **kw)
+    b = pf.solve_dagmf_static(D, S, p.graph, **kw)
+    _same(a, b)
+    with pytest.raises(pf.PseudoflowError) as ei:
+        pf.solve_dagmf_static(D, S, p.graph, kernel="fused", **kw)
+    assert ei.value.code == pf.PF_ENOMEM
 
 
 def _raw_params(**kw):
