@@ -219,6 +219,7 @@ FLOW_LABEL_CASES = {
     "dagmf_blobs_18x30x38_gap7": (lambda: WORKLOADS["dagmf_blobs_18x30x38"](), 7),
     "ishikawa_levels_20x36x44_n7": (lambda: WORKLOADS["ishikawa_levels_20x36x44_n7"](), 0),
     # chains in the chain builds of 4, 8, 12 and 16 labels, with padding labels
+    "ishikawa_2_labels": (lambda: synth.ishikawa_levels(shape=(9, 15, 66), n_levels=1), 0),
     "ishikawa_3_labels_gap5": (lambda: synth.ishikawa_levels(shape=(21, 13, 70), n_levels=2), 5),
     "ishikawa_5_labels": (lambda: synth.ishikawa_levels(shape=(19, 17, 40), n_levels=4), 0),
     "ishikawa_12_labels": (lambda: synth.ishikawa_levels(shape=(7, 12, 67), n_levels=11), 0),
